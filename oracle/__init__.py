@@ -1,0 +1,191 @@
+"""Python access to the FP64 CPU oracle (cme_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg use it; the solver package never imports it.  It shares no
+code with the HIP path.  Inputs are plain numpy arrays (typically drawn by the
+seeded generators of ``paper_1307_3428_amd.workloads``).
+
+What each call computes is documented in cme_oracle.c: the cyclic (or
+truncated) four-wave-mixing sum of Eq. (1)-(3) by O(N^2) correlations, the
+right-hand side of Eq. (1) in the rotating frame, classic RK4 (Sec. 2), its
+discrete adjoint, and the frequency-domain split-step map (Sec. 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "cme_oracle.c")
+LIB = os.path.join(_HERE, "libcme_oracle.so")
+
+# -fcx-limited-range only drops C99's Inf/NaN recovery in complex products;
+# no -ffast-math.  x86-64-v3 (AVX2/FMA) runs on every current x86 server.
+CFLAGS = ["-O3", "-march=x86-64-v3", "-fopenmp", "-fPIC", "-shared", "-fcx-limited-range",
+          "-std=gnu11", "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into oracle/libcme_oracle.so."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", *CFLAGS, "-o", tmp, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+class OrcInstance(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32), ("reserved", ctypes.c_int32), ("offset", ctypes.c_int64),
+        ("kappa_ext", ctypes.c_double), ("g0", ctypes.c_double),
+        ("ain_re", ctypes.c_double), ("ain_im", ctypes.c_double),
+        ("sigma0", ctypes.c_double), ("sigma1", ctypes.c_double), ("tau_ramp", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB):
+        build(force=False)
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sigs = {
+        "orc_set_threads": (None, [ctypes.c_int]),
+        "orc_max_threads": (ctypes.c_int, []),
+        "orc_fwm": (ctypes.c_int, [ctypes.c_int, P, P, ctypes.c_int]),
+        "orc_kerr_vjp": (ctypes.c_int, [ctypes.c_int, P, P, P]),
+        "orc_sigma": (dbl, [P, dbl]),
+        "orc_rhs": (ctypes.c_int, [P, P, P, dbl, P, P, ctypes.c_int]),
+        "orc_run": (ctypes.c_int, [ctypes.c_int, P, P, P, dbl, i64, i64, P, ctypes.c_int,
+                                   ctypes.c_int, P, i64]),
+        "orc_adjoint": (ctypes.c_int, [ctypes.c_int, P, P, P, dbl, i64, i64, P, P, P, P, P, P]),
+        "orc_split_step_run": (ctypes.c_int, [ctypes.c_int, P, P, P, dbl, i64, i64, P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def set_threads(n: int) -> None:
+    load().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(load().orc_max_threads())
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def fwm(a, truncated: bool = False) -> np.ndarray:
+    a = _c128(a)
+    K = np.empty_like(a)
+    _check(load().orc_fwm(int(a.shape[0]), _ptr(a), _ptr(K), int(truncated)), "fwm")
+    return K
+
+
+def kerr_vjp(u, w) -> np.ndarray:
+    u, w = _c128(u), _c128(w)
+    v = np.empty_like(u)
+    _check(load().orc_kerr_vjp(int(u.shape[0]), _ptr(u), _ptr(w), _ptr(v)), "kerr_vjp")
+    return v
+
+
+def _instances(packed) -> ctypes.Array:
+    arr = (OrcInstance * packed.batch)()
+    for b in range(packed.batch):
+        a_in = complex(packed.a_in[b])
+        arr[b] = OrcInstance(int(packed.n_modes[b]), 0, int(packed.offsets[b]),
+                             float(packed.kappa_ext[b]), float(packed.g0[b]),
+                             a_in.real, a_in.imag, float(packed.sigma0[b]),
+                             float(packed.sigma1[b]), float(packed.tau_ramp[b]))
+    return arr
+
+
+def sigma(packed, b: int, t: float) -> float:
+    arr = _instances(packed)
+    return float(load().orc_sigma(ctypes.byref(arr[b]), float(t)))
+
+
+def rhs(packed, b: int, t: float, u, truncated: bool = False) -> np.ndarray:
+    arr = _instances(packed)
+    sl = packed.slice(b)
+    kap, om = _f64(packed.kappa[sl]), _f64(packed.omega[sl])
+    u = _c128(u)
+    f = np.empty_like(u)
+    _check(load().orc_rhs(ctypes.byref(arr[b]), _ptr(kap), _ptr(om), float(t), _ptr(u), _ptr(f),
+                          int(truncated)), "rhs")
+    return f
+
+
+def run(packed, h: float, n_steps: int, step0: int = 0, y0=None, truncated: bool = False,
+        ckpt_every: int = 0) -> Tuple[np.ndarray, Optional[np.ndarray]]:
+    """Classic RK4 over the packed batch.  Returns (y(T), checkpoints or None)."""
+    arr = _instances(packed)
+    y = _c128(packed.a0 if y0 is None else y0).copy()
+    kap, om = _f64(packed.kappa), _f64(packed.omega)
+    ck = None
+    if ckpt_every > 0:
+        ck = np.zeros((n_steps // ckpt_every, packed.total), dtype=np.complex128)
+    rc = load().orc_run(packed.batch, arr, _ptr(kap), _ptr(om), float(h), int(step0),
+                        int(n_steps), _ptr(y), int(truncated), int(ckpt_every), _ptr(ck),
+                        int(packed.total))
+    _check(rc, "run")
+    return y, ck
+
+
+def adjoint(packed, h: float, n_steps: int, gT, step0: int = 0, y0=None):
+    """Discrete adjoint of `run` (cyclic).  Returns dict with the cotangent of
+    y(0), dL/domega', dL/dkappa and dL/dA_in (complex, per instance)."""
+    arr = _instances(packed)
+    y0 = _c128(packed.a0 if y0 is None else y0)
+    gT = _c128(gT)
+    kap, om = _f64(packed.kappa), _f64(packed.omega)
+    gy0 = np.zeros_like(y0)
+    g_om = np.zeros(packed.total)
+    g_kap = np.zeros(packed.total)
+    g_ain = np.zeros(packed.batch, dtype=np.complex128)
+    rc = load().orc_adjoint(packed.batch, arr, _ptr(kap), _ptr(om), float(h), int(step0),
+                            int(n_steps), _ptr(y0), _ptr(gT), _ptr(gy0), _ptr(g_om), _ptr(g_kap),
+                            _ptr(g_ain))
+    _check(rc, "adjoint")
+    return {"gy0": gy0, "g_omega": g_om, "g_kappa": g_kap, "g_ain": g_ain}
+
+
+def split_step_run(packed, h: float, n_steps: int, step0: int = 0, y0=None) -> np.ndarray:
+    arr = _instances(packed)
+    y = _c128(packed.a0 if y0 is None else y0).copy()
+    kap, om = _f64(packed.kappa), _f64(packed.omega)
+    rc = load().orc_split_step_run(packed.batch, arr, _ptr(kap), _ptr(om), float(h), int(step0),
+                                   int(n_steps), _ptr(y))
+    _check(rc, "split_step_run")
+    return y
