@@ -1,0 +1,180 @@
+/*
+ * cme.h -- C ABI of the MI355X (gfx950) solver for the Kerr-comb coupled mode
+ * equations (CME) of Hansson, Modotto & Wabnitz, "On the numerical simulation
+ * of Kerr frequency combs using coupled mode equations", arXiv:1307.3428.
+ *
+ * The solver time-steps Eq. (1) of the paper in the frame rotating with the
+ * pump and the FSR grid (the frame of Eq. (2), without its rescaling):
+ *
+ *   dA_mu/dtau = (-kappa_mu/2 + i(omega'_mu - sigma(tau))) A_mu
+ *                + [mu == 0] sqrt(kappa_ext) A_in + i g0 K_mu(A),
+ *
+ *   K_mu = sum over alpha - beta + gamma = mu (mod N) of A_alpha conj(A_beta) A_gamma,
+ *
+ * where omega'_mu = omega_mu - omega_0 - mu D1 (the FSR offset of Eq. (2) read
+ * as mu times the FSR) and sigma = omega_in - omega_0 (Eq. (1)).  The
+ * four-wave-mixing sum K is evaluated as in Eq. (4): an inverse transform of
+ * the mode amplitudes, the pointwise cube |a|^2 a, and a forward transform
+ * carrying the single 1/N; both transforms run as FFTs inside the GPU kernels.
+ * Time stepping is the classic fourth-order Runge-Kutta scheme named in
+ * Sec. 2 (stage times t, t+h/2, t+h/2, t+h; weights 1/6, 1/3, 1/3, 1/6).
+ *
+ * Conventions shared by every entry point
+ *   - An instance is one resonator.  Its N mode amplitudes are stored
+ *     contiguously in centred order: element i holds mode mu = i - N/2, so the
+ *     pump mode mu = 0 is element N/2.  N must be a power of two,
+ *     16 <= N <= 8192.
+ *   - A batch packs instances back to back; instance b starts at element
+ *     inst[b].mode_offset of every per-mode array (state, kappa, omega').
+ *     Ranges of different instances must not overlap.  "total" below is the
+ *     number of packed elements: max over b of mode_offset + n_modes.
+ *   - Complex arrays are interleaved (re, im) pairs: 16 bytes per element in
+ *     FP64 plans, 8 bytes in FP32 plans.
+ *   - Time enters only through the integer step index: step n of a call with
+ *     first step step0 is at tau = (step0 + n) * h.  Splitting a run into
+ *     several calls therefore gives bit-identical results.
+ *   - Device pointers are HIP device addresses on the device that was
+ *     current at cme_init.  The caller owns every pointer it passes; the
+ *     library never frees or reallocates caller memory.
+ *   - All compute calls are asynchronous on the plan's stream and return a
+ *     launch status.  Numerical failure (a non-finite amplitude) is reported
+ *     per instance by cme_status, which synchronises the stream.
+ */
+#ifndef CME_H
+#define CME_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes: 0 on success, negative on error (see cme_strerror). */
+enum {
+  CME_OK = 0,
+  CME_EINVAL = -1,       /* invalid argument: null pointer, N not a power of
+                            two or out of range, h <= 0, bad offsets, ...   */
+  CME_ENOMEM = -2,       /* device or host allocation failed                */
+  CME_EHIP = -3,         /* a HIP runtime call failed                       */
+  CME_EUNSTABLE = -4,    /* classic RK4 step outside its stability region:
+                            h * max_mu |-kappa_mu/2 + i(omega'_mu - sigma)|
+                            > 2 sqrt(2) for some instance and detuning      */
+  CME_ENONFINITE = -5,   /* non-finite input (kappa, omega', pump, ...)    */
+  CME_EUNSUPPORTED = -6, /* valid request this build does not provide      */
+  CME_ENODEVICE = -7     /* no gfx950 device / kernels not loadable        */
+};
+
+enum { CME_F64 = 0, CME_F32 = 1 };        /* arithmetic precision            */
+enum { CME_RK4 = 0 };                     /* integrator                      */
+enum { CME_FWM_CYCLIC = 0 };              /* FWM sum taken modulo N (Eq. (4)) */
+
+/* Flags of cme_init (bitwise or). */
+enum {
+  CME_INIT_DEFAULT = 0,
+  CME_INIT_SKIP_STABILITY = 1, /* do not refuse steps past the RK4 bound     */
+  CME_INIT_AUTOTUNE = 2        /* time the kernel variants for each N once and
+                                  keep the fastest (otherwise a fixed table) */
+};
+
+/* One resonator: the scalar symbols of Eq. (1). */
+typedef struct {
+  int32_t n_modes;      /* N: power of two, 16 <= N <= 8192                   */
+  int32_t reserved;     /* must be 0                                          */
+  int64_t mode_offset;  /* first element of this instance in per-mode arrays  */
+  double kappa_ext;     /* external coupling loss kappa_ext >= 0              */
+  double g0;            /* Kerr coefficient g0                                */
+  double a_in_re;       /* pump amplitude A_in (drives mu = 0 only)           */
+  double a_in_im;
+  double sigma0;        /* detuning sigma = omega_in - omega_0 at tau = 0     */
+  double sigma1;        /* detuning for tau >= tau_ramp                       */
+  double tau_ramp;      /* sigma(tau) = sigma0 + (sigma1 - sigma0)
+                           * min(tau, tau_ramp) / tau_ramp if tau_ramp > 0,
+                           sigma0 otherwise                                   */
+} cme_instance;
+
+typedef struct cme_plan cme_plan;
+
+/* Create a plan for a batch of `batch` instances (Eq. (1) parameters).
+ *   inst   host array [batch]; copied.
+ *   kappa  device array [total] of FP64 kappa_mu (total loss per mode); copied
+ *          into plan-owned memory, so it may be freed after the call.
+ *   omega  device array [total] of FP64 omega'_mu; copied likewise.
+ *   precision CME_F64 or CME_F32 (FP32 state and transforms; the time and
+ *          detuning bookkeeping stays FP64).
+ *   integrator CME_RK4.  fwm CME_FWM_CYCLIC.
+ *   h      step size (> 0) in the time units of kappa.
+ *   stream hipStream_t the plan enqueues on (NULL: the null stream).
+ *   flags  CME_INIT_* bits.
+ * The RK4 stability check uses the detuning range [min(sigma0, sigma1),
+ * max(sigma0, sigma1)] of every instance.  On error *plan is set to NULL. */
+int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst,
+             const double *kappa, const double *omega, int32_t precision,
+             int32_t integrator, int32_t fwm, double h, void *stream, uint32_t flags);
+
+/* Advance the packed state A (device, complex [total], in/out) by one RK4
+ * step from step index step0.  Same as cme_run with n_steps = 1. */
+int cme_step(cme_plan *plan, void *A, int64_t step0);
+
+/* Advance A by n_steps >= 0 RK4 steps starting at step index step0 >= 0.
+ * Each instance stays on one GPU workgroup for the whole call (persistent).
+ *   ckpt_every  0, or store the state after every ckpt_every steps into
+ *   ckpt        device complex [n_steps / ckpt_every][total]: slot j holds
+ *               A after (j + 1) * ckpt_every steps of this call. */
+int cme_run(cme_plan *plan, void *A, int64_t step0, int64_t n_steps,
+            int32_t ckpt_every, void *ckpt);
+
+/* Discrete adjoint of cme_run (not in the paper: the gradient form of the
+ * method).  Given the state A0 at step0 (device complex [total]) and the
+ * cotangent gA_T = dL/dRe A(T) + i dL/dIm A(T) of the state after n_steps
+ * steps, computes by checkpointed recomputation (segments of ckpt_every steps,
+ * 0 = one segment):
+ *   gA_0     device complex [total] or NULL: cotangent of A0 (written)
+ *   g_omega  device FP64 [total] or NULL: += dL/domega'_mu
+ *   g_kappa  device FP64 [total] or NULL: += dL/dkappa_mu
+ *   g_ain    device FP64 [2 * batch] or NULL: += (dL/dRe A_in, dL/dIm A_in)
+ * ckpt: device complex [n_steps / ckpt_every][total] as written by cme_run
+ * with the same step0 / ckpt_every, or NULL (the adjoint then runs the
+ * forward pass itself).  A0 is not modified.  Uses plan-owned device scratch
+ * of 4 * ckpt_every * total complex values (allocated on first use). */
+int cme_adjoint(cme_plan *plan, const void *A0, const void *ckpt, int64_t step0,
+                int64_t n_steps, int32_t ckpt_every, const void *gA_T, void *gA_0,
+                double *g_omega, double *g_kappa, double *g_ain);
+
+/* Synchronise the plan's stream and report per-instance status into the host
+ * array flags[batch] (0: finite; 1: a non-finite amplitude was seen).  Returns
+ * CME_ENONFINITE if any flag is set, CME_OK otherwise.  Clears the flags. */
+int cme_status(cme_plan *plan, int32_t *flags);
+
+/* Change the stream later calls enqueue on. */
+int cme_set_stream(cme_plan *plan, void *stream);
+
+/* Describe the kernel chosen for mode count n_modes: elements per thread,
+ * threads per instance, instances per workgroup.  CME_EINVAL if the plan has
+ * no instance of that size. */
+int cme_plan_kernel(const cme_plan *plan, int32_t n_modes, int32_t *elems_per_thread,
+                    int32_t *threads_per_instance, int32_t *instances_per_group);
+
+/* Force the kernel variant used for mode count n_modes: elems_per_thread is
+ * the number of modes each GPU thread owns (a power of two; the variants
+ * compiled for that size are listed by cme_list_kernels).  CME_EINVAL if the
+ * plan has no instance of that size, CME_EUNSUPPORTED if no such variant. */
+int cme_plan_select(cme_plan *plan, int32_t n_modes, int32_t elems_per_thread);
+
+/* Compiled kernel variants for a precision and mode count: writes up to `cap`
+ * elements-per-thread values into out[] and returns how many exist. */
+int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *out, int32_t cap);
+
+/* Release the plan and everything it owns.  NULL is accepted. */
+int cme_destroy(cme_plan *plan);
+
+/* Static description of a status code. */
+const char *cme_strerror(int code);
+
+/* Library version as major * 10000 + minor * 100 + patch. */
+int cme_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CME_H */

@@ -1,0 +1,520 @@
+// cme_api.hip -- host runtime behind the C ABI declared in include/cme.h.
+//
+// A plan owns: the per-instance device descriptors, copies of the per-mode
+// loss and frequency arrays, one twiddle table exp(-2 pi i k / N) per mode
+// count (computed on the host in long double), the per-size launch order,
+// the non-finite flags and, on first use, the adjoint's scratch.
+// Instances are grouped by mode count; each group runs as one persistent
+// launch of the kernel variant chosen for that size (fixed table, or the
+// fastest variant measured once when CME_INIT_AUTOTUNE is set).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/cme.h"
+#include "cme_internal.hpp"
+
+using cme::DevInst;
+using cme::Variant;
+
+namespace {
+
+struct SizeClass {
+  int n = 0;
+  const Variant *var = nullptr;
+  std::vector<int32_t> ids;
+  int32_t *d_order = nullptr;
+  void *d_tw = nullptr;
+};
+
+}  // namespace
+
+struct cme_plan {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int32_t batch = 0;
+  int32_t precision = CME_F64;
+  double h = 0.0;
+  uint32_t flags = 0;
+  int64_t total = 0;
+  size_t elem = 16;  // bytes per complex element
+  std::vector<cme_instance> inst;
+  DevInst *d_inst = nullptr;
+  double *d_kappa = nullptr;
+  double *d_omega = nullptr;
+  int32_t *d_flags = nullptr;
+  std::vector<SizeClass> classes;
+  // adjoint scratch (grown on demand)
+  void *d_stages = nullptr;
+  size_t stages_bytes = 0;
+  void *d_ckpt = nullptr;
+  size_t ckpt_bytes = 0;
+  void *d_state = nullptr;
+  size_t state_bytes = 0;
+  void *d_gA = nullptr;
+  size_t gA_bytes = 0;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                     \
+  do {                                    \
+    if ((expr) != hipSuccess) return CME_EHIP; \
+  } while (0)
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+// Default elements per thread for each mode count (FP64).
+int default_e(int n) {
+  switch (n) {
+    case 16: case 32: case 64: return 4;
+    case 4096: case 8192: return 16;
+    default: return 8;
+  }
+}
+
+const Variant *find_variant(int precision, int n, int e) {
+  int cnt = 0;
+  const Variant *v = cme::variants(&cnt);
+  for (int i = 0; i < cnt; ++i)
+    if (v[i].precision == precision && v[i].n == n && v[i].e == e) return &v[i];
+  return nullptr;
+}
+
+std::vector<const Variant *> candidates(int precision, int n) {
+  int cnt = 0;
+  const Variant *v = cme::variants(&cnt);
+  std::vector<const Variant *> out;
+  for (int i = 0; i < cnt; ++i)
+    if (v[i].precision == precision && v[i].n == n) out.push_back(&v[i]);
+  return out;
+}
+
+// Classic RK4 stability polynomial R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24.
+double rk4_growth(double zr, double zi) {
+  // Horner in complex arithmetic
+  double pr = 1.0 / 24.0, pi = 0.0;
+  const double c[4] = {1.0 / 6.0, 0.5, 1.0, 1.0};
+  for (double ck : c) {
+    const double nr = pr * zr - pi * zi + ck, ni = pr * zi + pi * zr;
+    pr = nr;
+    pi = ni;
+  }
+  return std::sqrt(pr * pr + pi * pi);
+}
+
+int upload_twiddles(int n, int precision, void **out) {
+  const size_t elem = precision == CME_F64 ? 16 : 8;
+  std::vector<unsigned char> host(elem * (size_t)n);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int k = 0; k < n; ++k) {
+    const long double ang = -two_pi * (long double)k / (long double)n;
+    const long double c = cosl(ang), s = sinl(ang);
+    if (precision == CME_F64) {
+      double v[2] = {(double)c, (double)s};
+      std::memcpy(&host[elem * k], v, 16);
+    } else {
+      float v[2] = {(float)c, (float)s};
+      std::memcpy(&host[elem * k], v, 8);
+    }
+  }
+  HIP_TRY(hipMalloc(out, host.size()));
+  HIP_TRY(hipMemcpy(*out, host.data(), host.size(), hipMemcpyHostToDevice));
+  return CME_OK;
+}
+
+int grow(void **p, size_t *have, size_t need) {
+  if (*have >= need) return CME_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *have = 0;
+  if (hipMalloc(p, need) != hipSuccess) {
+    *p = nullptr;
+    return CME_ENOMEM;
+  }
+  *have = need;
+  return CME_OK;
+}
+
+void free_plan(cme_plan *p) {
+  if (!p) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(p->device);
+  for (auto &c : p->classes) {
+    if (c.d_order) (void)hipFree(c.d_order);
+    if (c.d_tw) (void)hipFree(c.d_tw);
+  }
+  void *bufs[] = {p->d_inst, p->d_kappa, p->d_omega, p->d_flags, p->d_stages,
+                  p->d_ckpt, p->d_state, p->d_gA};
+  for (void *b : bufs)
+    if (b) (void)hipFree(b);
+  (void)hipSetDevice(cur);
+  delete p;
+}
+
+cme::RunArgs run_args(const cme_plan *p, const SizeClass &c, void *A, int64_t step0,
+                      int64_t n_steps, int32_t ckpt_every, void *ckpt, void *stages) {
+  cme::RunArgs a{};
+  a.inst = p->d_inst;
+  a.order = c.d_order;
+  a.count = (int32_t)c.ids.size();
+  a.ckpt_every = ckpt ? ckpt_every : 0;
+  a.A = A;
+  a.kappa = p->d_kappa;
+  a.omega = p->d_omega;
+  a.twiddle = c.d_tw;
+  a.h = p->h;
+  a.step0 = step0;
+  a.n_steps = n_steps;
+  a.ckpt = ckpt;
+  a.total = p->total;
+  a.flags = p->d_flags;
+  a.stages = stages;
+  return a;
+}
+
+int launch_forward(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
+                   void *ckpt, void *stages) {
+  for (auto &c : p->classes) {
+    const cme::RunArgs a = run_args(p, c, A, step0, n_steps, ckpt_every, ckpt, stages);
+    if (c.var->fwd(a, p->stream) != hipSuccess) return CME_EHIP;
+  }
+  return CME_OK;
+}
+
+// Time every compiled variant of each size once on plan-owned zero state and
+// keep the fastest.  Runs at init on the plan's stream.
+int autotune(cme_plan *p) {
+  void *state = nullptr;
+  const size_t bytes = p->elem * (size_t)p->total;
+  HIP_TRY(hipMalloc(&state, bytes));
+  int rc = CME_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = CME_EHIP;
+  if (rc == CME_OK && hipMemsetAsync(state, 0, bytes, p->stream) != hipSuccess) rc = CME_EHIP;
+  for (auto &c : p->classes) {
+    if (rc != CME_OK) break;
+    float best = 1e30f;
+    const Variant *pick = c.var;
+    // enough steps for a stable timing, scaled down for large sizes
+    const int64_t steps = std::max<int64_t>(4, (int64_t)(262144 / c.n));
+    for (const Variant *v : candidates(p->precision, c.n)) {
+      SizeClass tmp = c;
+      tmp.var = v;
+      const cme::RunArgs a = run_args(p, tmp, state, 0, steps, 0, nullptr, nullptr);
+      float ms = 0.f;
+      if (v->fwd(a, p->stream) != hipSuccess) { rc = CME_EHIP; break; }  // warm-up
+      if (hipEventRecord(e0, p->stream) != hipSuccess) { rc = CME_EHIP; break; }
+      if (v->fwd(a, p->stream) != hipSuccess) { rc = CME_EHIP; break; }
+      if (hipEventRecord(e1, p->stream) != hipSuccess) { rc = CME_EHIP; break; }
+      if (hipEventSynchronize(e1) != hipSuccess) { rc = CME_EHIP; break; }
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = CME_EHIP; break; }
+      if (ms < best) {
+        best = ms;
+        pick = v;
+      }
+    }
+    c.var = pick;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(p->stream);
+  (void)hipFree(state);
+  if (rc == CME_OK && hipMemsetAsync(p->d_flags, 0, sizeof(int32_t) * p->batch, p->stream) != hipSuccess)
+    rc = CME_EHIP;
+  return rc;
+}
+
+int validate_instances(int32_t batch, const cme_instance *inst, int64_t *total) {
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  ranges.reserve(batch);
+  int64_t tot = 0;
+  for (int32_t b = 0; b < batch; ++b) {
+    const cme_instance &x = inst[b];
+    if (!is_pow2(x.n_modes) || x.n_modes < 16 || x.n_modes > 8192) return CME_EINVAL;
+    if (x.reserved != 0 || x.mode_offset < 0) return CME_EINVAL;
+    const double vals[] = {x.kappa_ext, x.g0, x.a_in_re, x.a_in_im, x.sigma0, x.sigma1, x.tau_ramp};
+    for (double v : vals)
+      if (!std::isfinite(v)) return CME_ENONFINITE;
+    if (x.kappa_ext < 0.0 || x.tau_ramp < 0.0) return CME_EINVAL;
+    ranges.emplace_back(x.mode_offset, x.mode_offset + x.n_modes);
+    tot = std::max(tot, x.mode_offset + (int64_t)x.n_modes);
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second) return CME_EINVAL;
+  *total = tot;
+  return CME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cme_version(void) { return 10000; }
+
+const char *cme_strerror(int code) {
+  switch (code) {
+    case CME_OK: return "success";
+    case CME_EINVAL: return "invalid argument";
+    case CME_ENOMEM: return "out of memory";
+    case CME_EHIP: return "HIP runtime error";
+    case CME_EUNSTABLE: return "step size outside the RK4 stability region";
+    case CME_ENONFINITE: return "non-finite value";
+    case CME_EUNSUPPORTED: return "unsupported request";
+    case CME_ENODEVICE: return "no gfx950 device available";
+    default: return "unknown status code";
+  }
+}
+
+int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const double *kappa,
+             const double *omega, int32_t precision, int32_t integrator, int32_t fwm, double h,
+             void *stream, uint32_t flags) {
+  if (!plan) return CME_EINVAL;
+  *plan = nullptr;
+  if (batch <= 0 || !inst || !kappa || !omega) return CME_EINVAL;
+  if (precision != CME_F64 && precision != CME_F32) return CME_EINVAL;
+  if (integrator != CME_RK4 || fwm != CME_FWM_CYCLIC) return CME_EINVAL;
+  if (!(h > 0.0) || !std::isfinite(h)) return CME_EINVAL;
+  if (flags & ~(uint32_t)(CME_INIT_SKIP_STABILITY | CME_INIT_AUTOTUNE)) return CME_EINVAL;
+  int64_t total = 0;
+  int rc = validate_instances(batch, inst, &total);
+  if (rc != CME_OK) return rc;
+
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return CME_ENODEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return CME_ENODEVICE;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return CME_ENODEVICE;
+
+  // parameters to the host for validation (kappa / omega may be host or device)
+  std::vector<double> hk((size_t)total), ho((size_t)total);
+  if (hipMemcpy(hk.data(), kappa, sizeof(double) * total, hipMemcpyDefault) != hipSuccess ||
+      hipMemcpy(ho.data(), omega, sizeof(double) * total, hipMemcpyDefault) != hipSuccess)
+    return CME_EHIP;
+  for (int32_t b = 0; b < batch; ++b) {
+    const cme_instance &x = inst[b];
+    const double lo = std::min(x.sigma0, x.sigma1), hi = std::max(x.sigma0, x.sigma1);
+    for (int64_t i = x.mode_offset; i < x.mode_offset + x.n_modes; ++i) {
+      if (!std::isfinite(hk[i]) || !std::isfinite(ho[i])) return CME_ENONFINITE;
+      if (flags & CME_INIT_SKIP_STABILITY) continue;
+      for (double sg : {lo, hi}) {
+        const double zr = -0.5 * hk[i] * h, zi = (ho[i] - sg) * h;
+        if (rk4_growth(zr, zi) > 1.0 + 1e-12) return CME_EUNSTABLE;
+      }
+    }
+  }
+
+  cme_plan *p = new (std::nothrow) cme_plan();
+  if (!p) return CME_ENOMEM;
+  p->device = device;
+  p->stream = (hipStream_t)stream;
+  p->batch = batch;
+  p->precision = precision;
+  p->h = h;
+  p->flags = flags;
+  p->total = total;
+  p->elem = precision == CME_F64 ? 16 : 8;
+  p->inst.assign(inst, inst + batch);
+
+  std::vector<DevInst> dv((size_t)batch);
+  for (int32_t b = 0; b < batch; ++b) {
+    const cme_instance &x = inst[b];
+    const double sk = std::sqrt(x.kappa_ext);
+    DevInst &d = dv[b];
+    d.offset = x.mode_offset;
+    d.pump_re = sk * x.a_in_re;
+    d.pump_im = sk * x.a_in_im;
+    d.g0n = x.g0 / (double)x.n_modes;
+    d.sqrt_kext = sk;
+    d.sigma0 = x.sigma0;
+    d.sigma1 = x.sigma1;
+    d.tau_ramp = x.tau_ramp;
+    d.n = x.n_modes;
+    d.reserved = 0;
+  }
+  rc = CME_OK;
+  if (hipMalloc((void **)&p->d_inst, sizeof(DevInst) * batch) != hipSuccess ||
+      hipMalloc((void **)&p->d_kappa, sizeof(double) * total) != hipSuccess ||
+      hipMalloc((void **)&p->d_omega, sizeof(double) * total) != hipSuccess ||
+      hipMalloc((void **)&p->d_flags, sizeof(int32_t) * batch) != hipSuccess)
+    rc = CME_ENOMEM;
+  if (rc == CME_OK &&
+      (hipMemcpy(p->d_inst, dv.data(), sizeof(DevInst) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_kappa, hk.data(), sizeof(double) * total, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_omega, ho.data(), sizeof(double) * total, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemset(p->d_flags, 0, sizeof(int32_t) * batch) != hipSuccess))
+    rc = CME_EHIP;
+
+  // size classes, largest first (longest work first when they share the chip)
+  std::map<int, std::vector<int32_t>, std::greater<int>> groups;
+  for (int32_t b = 0; b < batch; ++b) groups[inst[b].n_modes].push_back(b);
+  for (auto &g : groups) {
+    if (rc != CME_OK) break;
+    SizeClass c;
+    c.n = g.first;
+    c.ids = g.second;
+    c.var = find_variant(precision, c.n, default_e(c.n));
+    if (!c.var) {
+      auto cand = candidates(precision, c.n);
+      if (cand.empty()) {
+        rc = CME_EUNSUPPORTED;
+        break;
+      }
+      c.var = cand.front();
+    }
+    if (hipMalloc((void **)&c.d_order, sizeof(int32_t) * c.ids.size()) != hipSuccess) {
+      rc = CME_ENOMEM;
+      p->classes.push_back(c);
+      break;
+    }
+    if (hipMemcpy(c.d_order, c.ids.data(), sizeof(int32_t) * c.ids.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      rc = CME_EHIP;
+    if (rc == CME_OK) rc = upload_twiddles(c.n, precision, &c.d_tw);
+    p->classes.push_back(c);
+  }
+  if (rc == CME_OK && (flags & CME_INIT_AUTOTUNE)) rc = autotune(p);
+  if (rc != CME_OK) {
+    free_plan(p);
+    return rc;
+  }
+  *plan = p;
+  return CME_OK;
+}
+
+int cme_set_stream(cme_plan *p, void *stream) {
+  if (!p) return CME_EINVAL;
+  p->stream = (hipStream_t)stream;
+  return CME_OK;
+}
+
+int cme_run(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
+            void *ckpt) {
+  if (!p || !A || step0 < 0 || n_steps < 0 || ckpt_every < 0) return CME_EINVAL;
+  if (ckpt && ckpt_every == 0) return CME_EINVAL;
+  if (n_steps == 0) return CME_OK;
+  if (n_steps > (int64_t)1 << 52) return CME_EINVAL;  // step index stays exact in FP64
+  return launch_forward(p, A, step0, n_steps, ckpt_every, ckpt, nullptr);
+}
+
+int cme_step(cme_plan *p, void *A, int64_t step0) { return cme_run(p, A, step0, 1, 0, nullptr); }
+
+int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, int64_t n_steps,
+                int32_t ckpt_every, const void *gA_T, void *gA_0, double *g_omega,
+                double *g_kappa, double *g_ain) {
+  if (!p || !A0 || !gA_T || step0 < 0 || n_steps < 0 || ckpt_every < 0) return CME_EINVAL;
+  if (ckpt && ckpt_every == 0) return CME_EINVAL;
+  if (p->precision != CME_F64) return CME_EUNSUPPORTED;
+  for (auto &c : p->classes)
+    if (!c.var->adj) return CME_EUNSUPPORTED;
+  const size_t vec = p->elem * (size_t)p->total;
+  if (n_steps == 0) {
+    if (gA_0) HIP_TRY(hipMemcpyAsync(gA_0, gA_T, vec, hipMemcpyDefault, p->stream));
+    return CME_OK;
+  }
+  const int64_t K = ckpt_every > 0 ? std::min<int64_t>(ckpt_every, n_steps) : n_steps;
+  if (K > (1 << 20)) return CME_EINVAL;
+  const int64_t nseg = (n_steps + K - 1) / K;
+  int rc = grow(&p->d_stages, &p->stages_bytes, vec * 4 * (size_t)K);
+  if (rc != CME_OK) return rc;
+  rc = grow(&p->d_state, &p->state_bytes, vec);
+  if (rc != CME_OK) return rc;
+  rc = grow(&p->d_gA, &p->gA_bytes, vec);
+  if (rc != CME_OK) return rc;
+  const unsigned char *ck = (const unsigned char *)ckpt;
+  if (!ck && nseg > 1) {
+    // no checkpoints given: run the forward pass once, keeping segment starts
+    rc = grow(&p->d_ckpt, &p->ckpt_bytes, vec * (size_t)(nseg - 1));
+    if (rc != CME_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(p->d_state, A0, vec, hipMemcpyDefault, p->stream));
+    rc = launch_forward(p, p->d_state, step0, (nseg - 1) * K, (int32_t)K, p->d_ckpt, nullptr);
+    if (rc != CME_OK) return rc;
+    ck = (const unsigned char *)p->d_ckpt;
+  }
+  HIP_TRY(hipMemcpyAsync(p->d_gA, gA_T, vec, hipMemcpyDefault, p->stream));
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t first = seg * K;
+    const int64_t len = std::min<int64_t>(K, n_steps - first);
+    const void *start = seg == 0 ? A0 : (const void *)(ck + (size_t)(seg - 1) * vec);
+    HIP_TRY(hipMemcpyAsync(p->d_state, start, vec, hipMemcpyDefault, p->stream));
+    rc = launch_forward(p, p->d_state, step0 + first, len, 0, nullptr, p->d_stages);
+    if (rc != CME_OK) return rc;
+    for (auto &c : p->classes) {
+      cme::AdjArgs a{};
+      a.inst = p->d_inst;
+      a.order = c.d_order;
+      a.count = (int32_t)c.ids.size();
+      a.n_seg = (int32_t)len;
+      a.stages = p->d_stages;
+      a.gA = p->d_gA;
+      a.kappa = p->d_kappa;
+      a.omega = p->d_omega;
+      a.twiddle = c.d_tw;
+      a.h = p->h;
+      a.step_first = step0 + first;
+      a.total = p->total;
+      a.g_omega = g_omega;
+      a.g_kappa = g_kappa;
+      a.g_ain = g_ain;
+      if (c.var->adj(a, p->stream) != hipSuccess) return CME_EHIP;
+    }
+  }
+  if (gA_0) HIP_TRY(hipMemcpyAsync(gA_0, p->d_gA, vec, hipMemcpyDefault, p->stream));
+  return CME_OK;
+}
+
+int cme_status(cme_plan *p, int32_t *flags) {
+  if (!p || !flags) return CME_EINVAL;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  HIP_TRY(hipMemcpy(flags, p->d_flags, sizeof(int32_t) * p->batch, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(p->d_flags, 0, sizeof(int32_t) * p->batch));
+  for (int32_t b = 0; b < p->batch; ++b)
+    if (flags[b]) return CME_ENONFINITE;
+  return CME_OK;
+}
+
+int cme_plan_kernel(const cme_plan *p, int32_t n_modes, int32_t *e, int32_t *t, int32_t *ipb) {
+  if (!p) return CME_EINVAL;
+  for (const auto &c : p->classes) {
+    if (c.n != n_modes) continue;
+    if (e) *e = c.var->e;
+    if (t) *t = c.var->n / c.var->e;
+    if (ipb) *ipb = c.var->ipb;
+    return CME_OK;
+  }
+  return CME_EINVAL;
+}
+
+int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t e) {
+  if (!p) return CME_EINVAL;
+  for (auto &c : p->classes) {
+    if (c.n != n_modes) continue;
+    const Variant *v = find_variant(p->precision, n_modes, e);
+    if (!v) return CME_EUNSUPPORTED;
+    c.var = v;
+    return CME_OK;
+  }
+  return CME_EINVAL;
+}
+
+int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *out, int32_t cap) {
+  const auto c = candidates(precision, n_modes);
+  for (size_t i = 0; i < c.size() && (int32_t)i < cap; ++i)
+    if (out) out[i] = c[i]->e;
+  return (int32_t)c.size();
+}
+
+int cme_destroy(cme_plan *p) {
+  if (!p) return CME_OK;
+  (void)hipStreamSynchronize(p->stream);
+  free_plan(p);
+  return CME_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,291 @@
+// cme_fft.hpp -- workgroup-resident complex FFT for gfx950 (CDNA4).
+//
+// Used twice per Runge-Kutta stage to evaluate the four-wave-mixing sum as in
+// Eq. (4) of Hansson, Modotto & Wabnitz (arXiv:1307.3428): an inverse
+// transform of the mode amplitudes, the pointwise cube, and a forward
+// transform.  The transforms are radix-E Stockham passes (E = elements per
+// thread, a power of two) whose data live in registers inside a pass and are
+// exchanged between passes through LDS.
+//
+// Ownership.  A team of T = N / E threads holds one length-N sequence; thread
+// t owns elements t + m T, m = 0..E-1, in registers.  In every pass the
+// thread's butterflies j = t + q T (q < E / R for radix R) read exactly those
+// elements, and in the final pass the Stockham output index of those
+// butterflies is again t + m T.  So a transform takes its input from and
+// leaves its output in the same registers: only the E - 1 exchanges between
+// passes touch LDS, and the RK4 state of mode t + m T can stay in the owning
+// thread's registers for the whole run.
+//
+// Pass (Stockham, decimation in time, natural order in and out), with
+// NS = product of the earlier radices and k = j mod NS:
+//   z_r  = x[j + r N / R] * exp(s 2 pi i r k / (NS R)),   r = 0..R-1
+//   Z    = DFT_R with sign s of z
+//   y[(j - k) R + k + r NS] = Z_r.
+// The radices are E, except one smaller pass (N / E^P) when N is not a power
+// of E; it is placed second.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <type_traits>
+
+namespace cme {
+
+// ---------------------------------------------------------------------------
+// Complex values and compile-time loops
+// ---------------------------------------------------------------------------
+template <typename Real> struct alignas(2 * sizeof(Real)) cx {
+  Real re, im;
+};
+
+template <typename Real>
+__device__ __forceinline__ cx<Real> cadd(cx<Real> a, cx<Real> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename Real>
+__device__ __forceinline__ cx<Real> csub(cx<Real> a, cx<Real> b) { return {a.re - b.re, a.im - b.im}; }
+// a * w
+template <typename Real>
+__device__ __forceinline__ cx<Real> cmul(cx<Real> a, cx<Real> w) {
+  return {a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re};
+}
+// a * conj(w)
+template <typename Real>
+__device__ __forceinline__ cx<Real> cmulc(cx<Real> a, cx<Real> w) {
+  return {a.re * w.re + a.im * w.im, a.im * w.re - a.re * w.im};
+}
+// a * exp(s i theta) given w = exp(-i theta): s = -1 -> a w, s = +1 -> a conj(w)
+template <int S, typename Real>
+__device__ __forceinline__ cx<Real> ctw(cx<Real> a, cx<Real> w) {
+  if constexpr (S < 0) return cmul(a, w);
+  else return cmulc(a, w);
+}
+
+template <int I> using ic = std::integral_constant<int, I>;
+
+// f(ic<B>), f(ic<B+1>), ..., f(ic<E-1>) with compile-time indices
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+  if constexpr (B < E) {
+    f(ic<B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+constexpr int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+// cos and sin of 2 pi j / 64 for j = 0..16, correctly rounded to double.
+struct Trig64 {
+  static constexpr double c[17] = {
+      1.0,                0.9951847266721969, 0.9807852804032304, 0.9569403357322088,
+      0.9238795325112867, 0.881921264348355,  0.8314696123025452, 0.773010453362737,
+      0.7071067811865476, 0.6343932841636455, 0.5555702330196022, 0.47139673682599764,
+      0.3826834323650898, 0.2902846772544624, 0.19509032201612828, 0.0980171403295606,
+      0.0};
+  // cos(2 pi j / 64) for any j (reduced mod 64)
+  static constexpr double cosj(int j) {
+    j = ((j % 64) + 64) % 64;
+    const int q = j / 16, r = j % 16;
+    return q == 0 ? c[r] : q == 1 ? -c[16 - r] : q == 2 ? -c[r] : c[16 - r];
+  }
+  static constexpr double sinj(int j) {
+    j = ((j % 64) + 64) % 64;
+    const int q = j / 16, r = j % 16;
+    return q == 0 ? c[16 - r] : q == 1 ? c[r] : q == 2 ? -c[16 - r] : -c[r];
+  }
+};
+
+// a * exp(S 2 pi i K / L), K and L compile-time, L a power of two dividing 64.
+// Multiplications by 0 or +-1 are never emitted: quarter turns are swaps and
+// sign flips, eighth turns two adds and two multiplies.
+template <int S, int K, int L, typename Real>
+__device__ __forceinline__ cx<Real> twc(cx<Real> a) {
+  static_assert(64 % L == 0, "twiddle denominator must divide 64");
+  constexpr int k = ((K % L) + L) % L;
+  constexpr int j = k * (64 / L);  // angle 2 pi j / 64
+  if constexpr (j == 0) {
+    return a;
+  } else if constexpr (j == 32) {
+    return {-a.re, -a.im};
+  } else if constexpr (j == 16 || j == 48) {
+    // exp(S i pi/2 * (1 or 3)) = +-i
+    constexpr int sg = (j == 16 ? 1 : -1) * (S > 0 ? 1 : -1);
+    if constexpr (sg > 0) return {-a.im, a.re};
+    else return {a.im, -a.re};
+  } else if constexpr (j % 8 == 0) {
+    // odd multiple of pi/4: (cs + i ss) / sqrt(2)
+    constexpr Real r = (Real)0.7071067811865476;
+    constexpr int cs = Trig64::cosj(j) > 0 ? 1 : -1;
+    constexpr int ss = (Trig64::sinj(j) > 0 ? 1 : -1) * (S > 0 ? 1 : -1);
+    const Real xr = cs > 0 ? a.re : -a.re, xi = cs > 0 ? a.im : -a.im;
+    const Real yr = ss > 0 ? a.im : -a.im, yi = ss > 0 ? a.re : -a.re;
+    return {r * (xr - yr), r * (xi + yi)};
+  } else {
+    constexpr Real c = (Real)Trig64::cosj(j);
+    constexpr Real s = (Real)(S > 0 ? Trig64::sinj(j) : -Trig64::sinj(j));
+    return {a.re * c - a.im * s, a.re * s + a.im * c};
+  }
+}
+
+constexpr int bitrev(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// In-register DFT of size R (power of two <= 64), sign S, natural order:
+// Z_k = sum_r z_r exp(S 2 pi i r k / R).  Radix-2 decimation in time on the
+// bit-reversed input (the permutation only renames registers).
+template <int R, int S, typename Real>
+__device__ __forceinline__ void dft_reg(cx<Real> (&z)[R]) {
+  if constexpr (R == 1) {
+    return;
+  } else {
+    constexpr int B = ilog2(R);
+    cx<Real> w[R];
+    sfor<0, R>([&](auto i) { w[bitrev(decltype(i)::value, B)] = z[decltype(i)::value]; });
+    sfor<1, B + 1>([&](auto lv) {
+      constexpr int len = 1 << decltype(lv)::value;
+      constexpr int half = len / 2;
+      sfor<0, R / len>([&](auto g) {
+        constexpr int base = decltype(g)::value * len;
+        sfor<0, half>([&](auto kk) {
+          constexpr int k = decltype(kk)::value;
+          const cx<Real> a = w[base + k];
+          const cx<Real> b = twc<S, k, len>(w[base + k + half]);
+          w[base + k] = cadd(a, b);
+          w[base + k + half] = csub(a, b);
+        });
+      });
+    });
+    sfor<0, R>([&](auto i) { z[decltype(i)::value] = w[decltype(i)::value]; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass plan for length N with E elements per thread
+// ---------------------------------------------------------------------------
+template <int N, int E> struct FftPlan {
+  static_assert((N & (N - 1)) == 0 && (E & (E - 1)) == 0 && E >= 2 && E <= N, "bad plan");
+  static constexpr int T = N / E;  // threads per sequence
+  static constexpr int LN = ilog2(N), LE = ilog2(E);
+  static constexpr int PFULL = LN / LE;
+  static constexpr int REM = 1 << (LN - PFULL * LE);
+  static constexpr int P = PFULL + (REM > 1 ? 1 : 0);
+  static constexpr int REMPOS = REM > 1 ? 1 : -1;
+
+  static constexpr int radix(int p) { return p == REMPOS ? REM : E; }
+  static constexpr int ns(int p) {
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= radix(i);
+    return s;
+  }
+  // number of distinct twiddle index sets per pass: k = (t + q T) mod NS
+  // depends on q only while NS > T
+  static constexpr int qd(int p) {
+    const int q = E / radix(p);
+    const int d = ns(p) > T ? ns(p) / T : 1;
+    return q < d ? q : d;
+  }
+  static constexpr int ntw(int p) { return p == 0 ? 0 : qd(p) * (radix(p) - 1); }
+  static constexpr int twoff(int p) {
+    int o = 0;
+    for (int i = 0; i < p; ++i) o += ntw(i);
+    return o;
+  }
+  static constexpr int NTW = twoff(P) > 0 ? twoff(P) : 1;
+};
+
+// LDS index with one padding element every 2^PS elements (PS = 0: none)
+template <int PS> __device__ __forceinline__ int lpad(int i) {
+  if constexpr (PS == 0) return i;
+  else return i + (i >> PS);
+}
+template <int N, int PS> struct LdsLen {
+  static constexpr int value = PS == 0 ? N : N + (N >> PS);
+};
+
+// Load the per-thread twiddles of every pass from the table
+// tab[i] = exp(-2 pi i i / N), i < N.
+template <int N, int E, typename Real>
+__device__ __forceinline__ void load_twiddles(cx<Real> (&tw)[(FftPlan<N, E>::NTW)],
+                                              const cx<Real> *__restrict__ tab, int t) {
+  using PL = FftPlan<N, E>;
+  sfor<1, PL::P>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), NSp = PL::ns(p), QD = PL::qd(p), OFF = PL::twoff(p);
+    constexpr int STRIDE = N / (NSp * R);
+    sfor<0, QD>([&](auto qi) {
+      constexpr int q = decltype(qi)::value;
+      const int k = (t + q * PL::T) & (NSp - 1);
+      sfor<1, R>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        tw[OFF + q * (R - 1) + (r - 1)] = tab[r * k * STRIDE];
+      });
+    });
+  });
+}
+
+// One transform of sign S (S = +1: a_j = sum_m x_m e^{+2 pi i j m / N};
+// S = -1: e^{-...}; no scaling) of the sequence held as v[m] = x[t + m T].
+// LDS: with PING (two buffers) each exchange alternates buffers starting at
+// parity PAR0 and needs one barrier; with a single buffer each exchange is
+// fenced by a barrier on both sides.  Returns the parity after the transform.
+template <int N, int E, int S, int PS, bool PING, int PAR0, typename Real>
+__device__ __forceinline__ void fft_team(cx<Real> (&v)[E], cx<Real> *__restrict__ buf0,
+                                         cx<Real> *__restrict__ buf1,
+                                         const cx<Real> (&tw)[(FftPlan<N, E>::NTW)], int t) {
+  using PL = FftPlan<N, E>;
+  constexpr int T = PL::T;
+  sfor<0, PL::P>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), NSp = PL::ns(p), QD = PL::qd(p), OFF = PL::twoff(p);
+    constexpr int Q = E / R;
+    constexpr bool LAST = p == PL::P - 1;
+    if constexpr (p > 0) {
+      cx<Real> *src = (PING && ((PAR0 + p - 1) & 1)) ? buf1 : buf0;
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        v[m] = src[lpad<PS>(t + m * T)];
+      });
+    }
+    if constexpr (!LAST && !PING) {
+      // single buffer: every thread must be done reading it (in the previous
+      // pass, or in the last pass of the previous transform) before it is
+      // overwritten
+      __syncthreads();
+    }
+    cx<Real> *dst = (PING && ((PAR0 + p) & 1)) ? buf1 : buf0;
+    sfor<0, Q>([&](auto qi) {
+      constexpr int q = decltype(qi)::value;
+      cx<Real> z[R];
+      sfor<0, R>([&](auto ri) { z[decltype(ri)::value] = v[q + decltype(ri)::value * Q]; });
+      if constexpr (NSp > 1) {
+        constexpr int qq = q % QD;
+        sfor<1, R>([&](auto ri) {
+          constexpr int r = decltype(ri)::value;
+          z[r] = ctw<S>(z[r], tw[OFF + qq * (R - 1) + (r - 1)]);
+        });
+      }
+      dft_reg<R, S>(z);
+      if constexpr (LAST) {
+        sfor<0, R>([&](auto ri) { v[q + decltype(ri)::value * Q] = z[decltype(ri)::value]; });
+      } else {
+        const int j = t + q * T;
+        const int k = j & (NSp - 1);
+        const int base = (j - k) * R + k;
+        sfor<0, R>([&](auto ri) {
+          constexpr int r = decltype(ri)::value;
+          dst[lpad<PS>(base + r * NSp)] = z[r];
+        });
+      }
+    });
+    if constexpr (!LAST) __syncthreads();
+  });
+}
+
+template <int N, int E> constexpr int fft_exchanges() { return FftPlan<N, E>::P - 1; }
+
+}  // namespace cme

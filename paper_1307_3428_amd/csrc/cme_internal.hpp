@@ -1,0 +1,83 @@
+// cme_internal.hpp -- structures shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cme {
+
+// Per-instance constants on the device (built by cme_init from cme_instance).
+struct DevInst {
+  int64_t offset;      // first element in the packed per-mode arrays
+  double pump_re;      // sqrt(kappa_ext) * A_in: the drive term of Eq. (1)
+  double pump_im;
+  double g0n;          // g0 / N: the forward transform carries the 1/N of Eq. (4)
+  double sqrt_kext;    // sqrt(kappa_ext), for the pump gradient
+  double sigma0, sigma1, tau_ramp;
+  int32_t n;
+  int32_t reserved;
+};
+
+// Arguments of one persistent forward launch over one size class.
+struct RunArgs {
+  const DevInst *inst;     // [batch]
+  const int32_t *order;    // instance ids of this class, in launch order
+  int32_t count;           // instances in this class
+  int32_t ckpt_every;      // 0: no checkpoints
+  void *A;                 // packed state, complex Real [total]
+  const double *kappa;     // packed kappa_mu [total]
+  const double *omega;     // packed omega'_mu [total]
+  const void *twiddle;     // exp(-2 pi i k / N), k < N, complex Real
+  double h;
+  int64_t step0;
+  int64_t n_steps;
+  void *ckpt;              // complex Real [n_steps / ckpt_every][total] or null
+  int64_t total;
+  int32_t *flags;          // [batch] non-finite flags
+  void *stages;            // adjoint recompute: stage inputs [K][4][total] or null
+};
+
+// Arguments of one reverse (adjoint) launch over one segment of one class.
+struct AdjArgs {
+  const DevInst *inst;
+  const int32_t *order;
+  int32_t count;
+  int32_t n_seg;           // steps in this segment
+  const void *stages;      // stage inputs u_s of every step of the segment [K][4][total]
+  void *gA;                // in: cotangent of the state after the segment; out: before
+  const double *kappa;
+  const double *omega;
+  const void *twiddle;
+  double h;
+  int64_t step_first;      // step index of the first step of the segment
+  int64_t total;
+  double *g_omega;         // [total] or null (accumulated)
+  double *g_kappa;         // [total] or null (accumulated)
+  double *g_ain;           // [2 batch] or null (accumulated)
+};
+
+__host__ __device__ inline double sigma_at(double sigma0, double sigma1, double tau_ramp,
+                                           double t) {
+  if (!(tau_ramp > 0.0)) return sigma0;
+  const double s = t < 0.0 ? 0.0 : (t > tau_ramp ? tau_ramp : t);
+  return sigma0 + (sigma1 - sigma0) * (s / tau_ramp);
+}
+
+using FwdLaunch = hipError_t (*)(const RunArgs &, hipStream_t);
+using AdjLaunch = hipError_t (*)(const AdjArgs &, hipStream_t);
+
+// One compiled kernel variant for a (precision, N, elements-per-thread) triple.
+struct Variant {
+  int precision;   // 0 FP64, 1 FP32
+  int n;           // modes
+  int e;           // elements per thread
+  int ipb;         // instances per workgroup
+  int threads;     // workgroup size
+  int lds_bytes;   // static LDS per workgroup
+  FwdLaunch fwd;
+  AdjLaunch adj;   // null if no adjoint kernel for this variant
+};
+
+const Variant *variants(int *count);
+
+}  // namespace cme

@@ -373,19 +373,22 @@ def fig1_ensemble(n_steps: Optional[int] = None, h: float = 1e-3, noise: float =
                     description="Fig. 1 parameter set, 4 pump levels")
 
 
-def random_batch(seed: int, sizes: Sequence[int], *, noise: float = 1e-3, d2_range=(1e-4, 2e-2),
-                 sigma_range=(-2.0, 6.0), pump_range=(0.5, 6.0), random_kappa: bool = True,
-                 random_phase_pump: bool = True) -> List[Instance]:
+def random_batch(seed: int, sizes: Sequence[int], *, noise: float = 1e-3,
+                 max_detuning: float = 40.0, sigma_range=(-2.0, 6.0), pump_range=(0.5, 6.0),
+                 random_kappa: bool = True, random_phase_pump: bool = True) -> List[Instance]:
     """Generic seeded instances for parity tests: random per-mode kappa and
-    omega' profiles, complex pump, sigma ramp, CW + noise start."""
+    omega' profiles (the dispersion is scaled with N so that max |omega'| stays
+    below `max_detuning`), complex pump, detuning ramp, CW + noise start."""
     rng = np.random.default_rng(seed)
     out = []
     for n in sizes:
+        half = max(1, n // 2)
         kap0 = float(rng.uniform(0.8, 1.2))
         kappa = kap0 * (1.0 + (0.2 * rng.uniform(-1, 1, n) if random_kappa else 0.0))
         kappa[n // 2] = kap0
-        d2 = float(rng.uniform(*d2_range))
-        omega = dispersion_profile(n, d2, float(rng.uniform(-1e-4, 1e-4)))
+        d2 = float(rng.uniform(0.05, 0.9)) * max_detuning * 2.0 / half ** 2
+        d3 = float(rng.uniform(-1.0, 1.0)) * 0.1 * max_detuning * 6.0 / half ** 3
+        omega = dispersion_profile(n, d2, d3)
         omega += rng.uniform(-0.05, 0.05, n)
         omega[n // 2] = 0.0
         kext = float(rng.uniform(0.2, 0.6)) * kap0

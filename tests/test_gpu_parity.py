@@ -1,0 +1,215 @@
+"""GPU parity: the HIP solver (through the C ABI) against the FP64 CPU oracle.
+
+Bar (FP64): relative L2 error of the complex amplitudes per instance
+<= 1e-10 (the tolerance the method is held to), and far tighter for the
+few-step cases, where only rounding separates the O(N^2) direct sum of the
+oracle from the GPU's FFT evaluation.  Integer bookkeeping (split runs,
+checkpoints) must be bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1307_3428_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def cme():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1307_3428_amd import cme as C
+    C.load_library()
+    return C
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def per_instance_err(packed, y_gpu, y_orc):
+    return [rel_err(y_gpu[packed.slice(b)], y_orc[packed.slice(b)]) for b in range(packed.batch)]
+
+
+def gpu_run(C, packed, h, steps, step0=0, e=None, n=None, flags=0):
+    import torch
+    with C.Plan(packed, h, flags=flags) as plan:
+        if e is not None:
+            plan.select(n, e)
+        A = plan.state(packed.a0)
+        plan.run(A, steps, step0=step0)
+        torch.cuda.synchronize()
+        st = plan.status()
+        return A.cpu().numpy(), st
+
+
+def moderate_batch(seed, sizes):
+    """Random per-mode kappa / omega', complex pump, detuning ramp, and a
+    full-support noisy state of total power ~1 so that every mode takes part
+    in the four-wave mixing."""
+    insts = W.random_batch(seed, sizes, noise=1.0)
+    for inst in insts:
+        inst.a0 = inst.a0 / math.sqrt(inst.n_modes)
+        inst.a0[inst.n_modes // 2] += 0.5
+    return insts
+
+
+def _variants():
+    from paper_1307_3428_amd import cme as C
+    out = []
+    for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        try:
+            es = C.cme_list_kernels(C.CME_F64, n)
+        except RuntimeError:
+            es = []
+        for e in es:
+            out.append((n, e))
+    return out
+
+
+def _variant_params():
+    try:
+        return _variants()
+    except Exception:
+        return [(16, 4)]
+
+
+@pytest.mark.parametrize("n,e", _variant_params())
+def test_each_kernel_variant_matches_oracle(cme, orc, n, e):
+    print(f"variant N={n} E={e}", flush=True)
+    batch = 3 if n <= 1024 else 2
+    insts = moderate_batch(1000 + n + e, [n] * batch)
+    p = W.pack(insts)
+    steps, h = 4, 0.01
+    y, st = gpu_run(cme, p, h, steps, step0=5, e=e, n=n)
+    ref, _ = orc.run(p, h, steps, step0=5)
+    errs = per_instance_err(p, y, ref)
+    assert max(errs) <= 1e-13, errs
+    assert not st.any()
+
+
+def test_mixed_sizes_in_one_plan(cme, orc):
+    sizes = [16, 2048, 64, 128, 16, 1024, 256, 512, 32, 4096]
+    insts = moderate_batch(77, sizes)
+    p = W.pack(insts)
+    y, st = gpu_run(cme, p, 0.005, 25)
+    ref, _ = orc.run(p, 0.005, 25)
+    errs = per_instance_err(p, y, ref)
+    assert max(errs) <= 1e-12, errs
+    assert not st.any()
+
+
+def test_plain_n128_full_horizon(cme, orc):
+    """Single instance N=128 (mu = -64..63), the plain-method workload at its
+    full horizon of 2e4 RK4 steps."""
+    wl = W.plain_n128()
+    p = W.pack(wl.instances)
+    y, st = gpu_run(cme, p, wl.h, wl.n_steps)
+    ref, _ = orc.run(p, wl.h, wl.n_steps)
+    err = rel_err(y, ref)
+    print(f"plain_n128 rel err {err:.3e}")
+    assert err <= FP64_TOL
+    assert not st.any()
+
+
+def test_turing_n128_pattern(cme, orc):
+    """Inside the MI band a Turing pattern grows from noise and saturates
+    (non-chaotic): parity over 3e4 steps, and the pattern is really there."""
+    wl = W.turing_n128(n_steps=30000)
+    p = W.pack(wl.instances)
+    y, _ = gpu_run(cme, p, wl.h, wl.n_steps)
+    ref, _ = orc.run(p, wl.h, wl.n_steps)
+    err = rel_err(y, ref)
+    print(f"turing_n128 rel err {err:.3e}")
+    assert err <= FP64_TOL
+    side = np.abs(ref) ** 2
+    side[64] = 0
+    assert side.max() > 1e-4        # sidebands grew from the 1e-8 noise floor
+
+
+def test_sweep_full_launch_sampled(cme, orc):
+    """The 256 x N=2048 detuning sweep in its full launch configuration for a
+    short horizon; sampled instances (both detuning ends and the middle)
+    against the oracle."""
+    wl = W.sweep_n2048(n_steps=100)
+    p = W.pack(wl.instances)
+    y, st = gpu_run(cme, p, wl.h, wl.n_steps)
+    pick = [0, 1, 100, 128, 254, 255]
+    sub = W.pack([wl.instances[i] for i in pick])
+    ref, _ = orc.run(sub, wl.h, wl.n_steps)
+    for j, i in enumerate(pick):
+        err = rel_err(y[p.slice(i)], ref[sub.slice(j)])
+        assert err <= 1e-12, (i, err)
+    assert not st.any()
+
+
+def test_split_run_is_bitwise(cme):
+    import torch
+    insts = moderate_batch(5, [256, 2048, 64])
+    p = W.pack(insts)
+    with cme.Plan(p, 0.01) as plan:
+        A1 = plan.state(p.a0)
+        plan.run(A1, 30, step0=3)
+        A2 = plan.state(p.a0)
+        plan.run(A2, 12, step0=3)
+        plan.run(A2, 1, step0=15)
+        plan.step(A2, 16)
+        plan.run(A2, 16, step0=17)
+        torch.cuda.synchronize()
+        assert torch.equal(A1, A2)
+
+
+def test_checkpoints_bitwise(cme):
+    import torch
+    insts = moderate_batch(6, [128, 1024])
+    p = W.pack(insts)
+    with cme.Plan(p, 0.01) as plan:
+        A = plan.state(p.a0)
+        ck = torch.zeros((3, p.total), dtype=torch.complex128, device="cuda")
+        plan.run(A, 31, ckpt_every=10, ckpt=ck)
+        for j in range(3):
+            B = plan.state(p.a0)
+            plan.run(B, 10 * (j + 1))
+            torch.cuda.synchronize()
+            assert torch.equal(ck[j], B)
+
+
+def test_nonfinite_flag_is_per_instance(cme):
+    import torch
+    insts = moderate_batch(7, [64, 64, 256])
+    insts[1].a0[3] = complex(float("nan"), 0.0)
+    p = W.pack(insts)
+    with cme.Plan(p, 0.01) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 3)
+        flags = plan.status()
+        assert list(flags) == [0, 1, 0]
+        assert list(plan.status()) == [0, 0, 0]     # cleared after reading
+        out = A.cpu().numpy()
+        assert np.isfinite(out[p.slice(0)]).all() and np.isfinite(out[p.slice(2)]).all()
+
+
+def test_adjoint_matches_oracle(cme, orc):
+    import torch
+    insts = moderate_batch(8, [64, 256, 16])
+    p = W.pack(insts)
+    h, steps, K = 0.01, 23, 7
+    rng = np.random.default_rng(8)
+    target = rng.uniform(0, 0.01, p.total)
+    yT, _ = orc.run(p, h, steps)
+    gT = 4 * (np.abs(yT) ** 2 - target) * yT
+    ref = orc.adjoint(p, h, steps, gT)
+    with cme.Plan(p, h) as plan:
+        A0 = plan.state(p.a0)
+        g = plan.adjoint(A0, plan.state(gT), steps, ckpt_every=K)
+        torch.cuda.synchronize()
+        assert torch.equal(A0, plan.state(p.a0))      # input untouched
+    assert rel_err(g["gA_0"].cpu().numpy(), ref["gy0"]) <= 1e-11
+    assert rel_err(g["g_omega"].cpu().numpy(), ref["g_omega"]) <= 1e-11
+    assert rel_err(g["g_kappa"].cpu().numpy(), ref["g_kappa"]) <= 1e-11
+    gain = g["g_ain"].cpu().numpy().reshape(-1, 2)
+    assert rel_err(gain[:, 0] + 1j * gain[:, 1], ref["g_ain"]) <= 1e-11
