@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark of the CME solver on one MI355X.
+
+Workload (default): the batched detuning sweep -- 256 resonators of N = 2048
+modes, D2 = 0.002, D3 = 2e-6, sigma_i evenly spaced in [-2, 10], pump 5x
+threshold, noise 1e-6, classic RK4 with h = 5e-4 for 5e4 steps, FP64.  One
+bench step is one full run of that horizon for the whole batch (one
+persistent kernel launch).  The metric is mode-steps/s = sum_i N_i x RK4
+steps / wall time, valid only where the GPU matches the FP64 oracle to
+<= 1e-10 relative L2 error; that error is measured here on a sampled
+subset over a short horizon, on the same launch configuration.
+
+Also reported on the same JSON line:
+  roofline      counted FFT flops (8 transforms x 5 N log2 N per RK4 step)
+                per launch / the launch's mean duration (HIP events on the
+                launch stream) against the FP64 vector peak (78.6 TFLOP/s);
+  cpu_baseline  the CPU oracle (O(N^2) direct sum) timed on a bounded
+                sample of the same workload on this host's cores;
+  adjoint       forward-with-checkpoints and adjoint times for the N = 2048,
+                5000-step gradient workload and their ratio;
+  single        a single N = 1024 instance (soliton ramp) on one workgroup.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "mode-steps/s (FP64, 1 GPU) at ≤1e-10 rel. error vs oracle; adjoint/forward ratio"
+FP64_PEAK_TFLOPS = 78.6
+COUNTERS = os.path.join(ROOT, "profiles", "rk4_persistent_sweep_n2048_counters.txt")
+KERNEL_SOURCES = ("cme_fft.hpp", "cme_kernels.hip", "cme_wave.hip", "cme_internal.hpp")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1307_3428_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n_launch_units: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if there is none or the kernel sources changed since."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        fetch = float(vals["fetch_kib_per_dispatch_scaled"]) * 1024.0
+        write = float(vals["write_kib_per_dispatch_scaled"]) * 1024.0
+        units = float(vals["rk4_steps_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * (n_launch_units / units)
+
+
+def counted_flops_per_step(n: int) -> float:
+    return 8 * 5.0 * n * math.log2(n)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed full runs")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed full runs")
+    ap.add_argument("--rk-steps", type=int, default=None,
+                    help="RK4 steps per run (default: the workload's 5e4)")
+    ap.add_argument("--parity-steps", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip adjoint / single-instance legs")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--kernel", type=int, default=-1, help="force a kernel variant id")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this solver benchmark runs on exactly one GPU; independent instances "
+              "would be sharded across GPUs with no communication, which this build does not "
+              "launch. Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1307_3428_amd import cme as C
+    from paper_1307_3428_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        n = 1 << 27  # 2^27 complex64 = 1 GiB
+        src = torch.ones(n, dtype=torch.complex64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8}))
+        return 0
+
+    rk_steps = args.rk_steps or 50000
+    wl = W.sweep_n2048(n_steps=rk_steps)
+    p = W.pack(wl.instances)
+    n_modes = 2048
+    flags = 0 if args.no_autotune else C.CME_INIT_AUTOTUNE
+    stream = torch.cuda.current_stream()
+    plan = C.Plan(p, wl.h, flags=flags)
+    if args.kernel >= 0:
+        plan.select(n_modes, args.kernel)
+    kinfo = plan.kernel(n_modes)
+    A0 = plan.state(p.a0)
+
+    # ---- parity on a sample, same launch configuration (all 256 instances) ----
+    parity, cpu_s, threads, sub, pick = None, None, None, None, []
+    if args.parity_steps > 0:
+        import oracle
+        pick = [0, 32, 64, 96, 128, 160, 192, 224, 255][: max(1, min(9, p.batch))]
+        A = A0.clone()
+        plan.run(A, args.parity_steps)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        sub = W.pack([wl.instances[i] for i in pick])
+        threads = oracle.max_threads()
+        t0 = time.perf_counter()
+        ref, _ = oracle.run(sub, wl.h, args.parity_steps)
+        cpu_s = time.perf_counter() - t0
+        errs = []
+        for j, i in enumerate(pick):
+            a, b = y[p.slice(i)], ref[sub.slice(j)]
+            errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+        parity = {"max_rel_l2_err": max(errs), "instances": pick, "rk4_steps": args.parity_steps,
+                  "tolerance": 1e-10, "ok": max(errs) <= 1e-10}
+    flags_out = plan.status()
+
+    # ---- timed runs ----
+    A = A0.clone()
+    for _ in range(args.warmup):
+        plan.run(A, rk_steps)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(stream)
+        plan.run(A, rk_steps)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    launch_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    mean_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
+    mode_steps = p.total * rk_steps * args.steps
+    value = mode_steps / wall
+    flops_per_launch = counted_flops_per_step(n_modes) * p.batch * rk_steps
+    achieved = flops_per_launch / mean_launch_s / 1e12
+    finite = not plan.status().any() and not flags_out.any()
+
+    traffic = read_traffic(p.batch * rk_steps)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "mode-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "sweep_n2048: 256 instances x N=2048 modes, RK4 h=5e-4, "
+                        f"{rk_steps} steps per bench step, sigma in [-2,10], pump 5x threshold",
+            "batch": p.batch, "n_modes": n_modes, "rk4_steps": rk_steps, "h": wl.h,
+            "kernel": {**kinfo, "autotuned": not args.no_autotune and args.kernel < 0},
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": traffic,
+            "counted_flops_per_launch": flops_per_launch,
+            "mean_launch_ms": mean_launch_s * 1e3,
+            "note": "counted flops = 8 FFTs x 5 N log2 N per RK4 step per instance; "
+                    "FP64 vector peak",
+        },
+        "parity": parity,
+        "all_finite": bool(finite),
+    }
+    if not args.no_cpu_baseline and cpu_s is not None:
+        out["cpu_baseline"] = {
+            "value": sub.total * args.parity_steps / cpu_s,
+            "unit": "mode-steps/s",
+            "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(pick)} of the 256 N=2048 instances x {args.parity_steps} RK4 steps "
+                      f"(O(N^2) direct-sum FWM, FP64, OpenMP), {cpu_s:.1f} s",
+        }
+    plan.close()
+
+    if not args.no_extras:
+        out["adjoint"] = adjoint_leg(C, W, torch)
+        out["single"] = single_leg(C, W, torch)
+    print(json.dumps(out))
+    return 0
+
+
+def adjoint_leg(C, W, torch):
+    """N=2048, 5000 RK4 steps, checkpoints every 100: forward (with
+    checkpoint writes) vs cme_adjoint (segment recompute + reverse sweep)."""
+    wl = W.adjoint_n2048()
+    p = W.pack(wl.instances)
+    K = 100
+    with C.Plan(p, wl.h) as plan:
+        A0 = plan.state(p.a0)
+        ck = torch.empty((wl.n_steps // K, p.total), dtype=torch.complex128, device="cuda")
+        gT = torch.ones_like(A0)
+        # warm-up
+        A = A0.clone()
+        plan.run(A, 200, ckpt_every=K, ckpt=ck[:2])
+        plan.adjoint(A0, gT, 200, ckpt_every=K, ckpt=ck[:2])
+        torch.cuda.synchronize()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        A = A0.clone()
+        e[0].record()
+        plan.run(A, wl.n_steps, ckpt_every=K, ckpt=ck)
+        e[1].record()
+        plan.adjoint(A0, gT, wl.n_steps, ckpt_every=K, ckpt=ck)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd, bwd = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    return {"workload": "adjoint_n2048: N=2048, 5000 RK4 steps, checkpoints every 100",
+            "forward_ms": fwd, "adjoint_ms": bwd, "adjoint_over_forward": bwd / fwd,
+            "forward_plus_adjoint_over_forward": (fwd + bwd) / fwd}
+
+
+def single_leg(C, W, torch):
+    """One N=1024 instance on one workgroup: soliton ramp workload, 20000 steps."""
+    steps = 20000
+    wl = W.soliton_ramp_n1024(n_steps=steps)
+    p = W.pack(wl.instances)
+    with C.Plan(p, wl.h, flags=C.CME_INIT_AUTOTUNE) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 1000)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.run(A, steps, step0=1000)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        k = plan.kernel(1024)
+    return {"workload": "soliton_ramp_n1024 (one instance), 20000 RK4 steps",
+            "mode_steps_per_s": 1024 * steps / (ms / 1e3), "us_per_rk4_step": ms * 1e3 / steps,
+            "kernel": k}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

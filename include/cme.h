@@ -148,21 +148,31 @@ int cme_status(cme_plan *plan, int32_t *flags);
 /* Change the stream later calls enqueue on. */
 int cme_set_stream(cme_plan *plan, void *stream);
 
-/* Describe the kernel chosen for mode count n_modes: elements per thread,
- * threads per instance, instances per workgroup.  CME_EINVAL if the plan has
- * no instance of that size. */
-int cme_plan_kernel(const cme_plan *plan, int32_t n_modes, int32_t *elems_per_thread,
-                    int32_t *threads_per_instance, int32_t *instances_per_group);
+/* Kernel variants.  Each compiled kernel variant has an integer id.  A plan
+ * uses one variant per mode count present in its batch: a fixed default, or
+ * the fastest measured one with CME_INIT_AUTOTUNE, or the one forced by
+ * cme_plan_select. */
 
-/* Force the kernel variant used for mode count n_modes: elems_per_thread is
- * the number of modes each GPU thread owns (a power of two; the variants
- * compiled for that size are listed by cme_list_kernels).  CME_EINVAL if the
- * plan has no instance of that size, CME_EUNSUPPORTED if no such variant. */
-int cme_plan_select(cme_plan *plan, int32_t n_modes, int32_t elems_per_thread);
+/* Id of the variant the plan uses for mode count n_modes.  CME_EINVAL if the
+ * plan has no instance of that size. */
+int cme_plan_kernel(const cme_plan *plan, int32_t n_modes, int32_t *kernel_id);
 
-/* Compiled kernel variants for a precision and mode count: writes up to `cap`
- * elements-per-thread values into out[] and returns how many exist. */
-int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *out, int32_t cap);
+/* Force variant kernel_id for mode count n_modes.  CME_EINVAL if the plan has
+ * no instance of that size, CME_EUNSUPPORTED if the id is not a variant for
+ * that size and the plan's precision. */
+int cme_plan_select(cme_plan *plan, int32_t n_modes, int32_t kernel_id);
+
+/* Ids of the variants compiled for a precision and mode count: writes up to
+ * `cap` ids into ids[] and returns how many exist. */
+int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t cap);
+
+/* Shape of variant kernel_id, written into info[0..min(cap, 9)-1]:
+ * precision, modes N, modes per thread E, wave-local sub-transforms per wave
+ * V, LDS padding shift (one pad element every 2^shift), kind (0: one
+ * transform per team of threads with workgroup barriers, 1: two-level
+ * transform with one workgroup barrier per transform), instances per
+ * workgroup, workgroup size, LDS bytes.  Returns 9, or CME_EINVAL. */
+int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 
 /* Release the plan and everything it owns.  NULL is accepted. */
 int cme_destroy(cme_plan *plan);

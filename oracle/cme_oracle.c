@@ -78,6 +78,10 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
 
 static int g_threads = 0; /* 0: OpenMP default */
 
+/* Inner loops of one state are split over threads only from this size on:
+ * below it the fork/join cost of a parallel region exceeds the work. */
+#define ORC_PAR_MIN_N 512
+
 void orc_set_threads(int n) { g_threads = n; }
 
 int orc_max_threads(void) {
@@ -94,7 +98,7 @@ int orc_max_threads(void) {
  * ------------------------------------------------------------------------- */
 static void fwm_cyclic(int n, const cplx *a, cplx *K, cplx *C, int par) {
   /* C_k = sum_gamma conj(A_{gamma+k}) A_gamma */
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int k = 0; k < n; ++k) {
     cplx s = 0.0;
     /* gamma + k, reduced mod N: the two ranges of gamma are summed in order */
@@ -103,7 +107,7 @@ static void fwm_cyclic(int n, const cplx *a, cplx *K, cplx *C, int par) {
     C[k] = s;
   }
   /* K_mu = sum_k A_{mu+k} C_k */
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int mu = 0; mu < n; ++mu) {
     cplx s = 0.0;
     for (int k = 0; k < n - mu; ++k) s += a[mu + k] * C[k];
@@ -115,7 +119,7 @@ static void fwm_cyclic(int n, const cplx *a, cplx *K, cplx *C, int par) {
 /* Truncated sum: alpha, beta, gamma, mu all inside [0, N) with
  * alpha - beta + gamma = mu exactly.  C is indexed by k + (N-1), k in (-N, N). */
 static void fwm_truncated(int n, const cplx *a, cplx *K, cplx *C, int par) {
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int k = -(n - 1); k <= n - 1; ++k) {
     cplx s = 0.0;
     for (int g = 0; g < n; ++g) {
@@ -124,7 +128,7 @@ static void fwm_truncated(int n, const cplx *a, cplx *K, cplx *C, int par) {
     }
     C[k + n - 1] = s;
   }
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int mu = 0; mu < n; ++mu) {
     cplx s = 0.0;
     for (int k = -(n - 1); k <= n - 1; ++k) {
@@ -153,7 +157,7 @@ int orc_fwm(int n, const cplx *a, cplx *K, int truncated) {
  * the second transposes the term linear in conj(du) (beta). */
 static void kerr_vjp_cyclic(int n, const cplx *u, const cplx *w, cplx *v, cplx *C, cplx *S,
                             int par) {
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int d = 0; d < n; ++d) {
     cplx c = 0.0, s = 0.0;
     for (int b = 0; b < n - d; ++b) c += conj(u[b + d]) * u[b];
@@ -163,7 +167,7 @@ static void kerr_vjp_cyclic(int n, const cplx *u, const cplx *w, cplx *v, cplx *
     C[d] = c;
     S[d] = s;
   }
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int nu = 0; nu < n; ++nu) {
     cplx acc = 0.0;
     for (int d = 0; d < n - nu; ++d) acc += 2.0 * w[nu + d] * C[d];
@@ -411,7 +415,7 @@ int orc_adjoint(int batch, const orc_instance *inst, const double *kappa, const 
  * ------------------------------------------------------------------------- */
 static void naive_dft(int n, const cplx *x, cplx *y, double sign, int par) {
   const double w0 = sign * 2.0 * M_PI / (double)n;
-#pragma omp parallel for schedule(static) if (par) num_threads(orc_max_threads())
+#pragma omp parallel for schedule(static) if (par && n >= ORC_PAR_MIN_N) num_threads(orc_max_threads())
   for (int j = 0; j < n; ++j) {
     cplx s = 0.0;
     for (int m = 0; m < n; ++m) {

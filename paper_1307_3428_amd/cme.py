@@ -28,9 +28,12 @@ CME_INIT_DEFAULT, CME_INIT_SKIP_STABILITY, CME_INIT_AUTOTUNE = 0, 1, 2
 
 EXPORTED = (
     "cme_init", "cme_step", "cme_run", "cme_adjoint", "cme_status", "cme_set_stream",
-    "cme_plan_kernel", "cme_plan_select", "cme_list_kernels", "cme_destroy", "cme_strerror",
-    "cme_version",
+    "cme_plan_kernel", "cme_plan_select", "cme_list_kernels", "cme_kernel_info", "cme_destroy",
+    "cme_strerror", "cme_version",
 )
+
+KERNEL_INFO_FIELDS = ("precision", "n_modes", "elems_per_thread", "sub_transforms", "pad_shift",
+                      "kind", "instances_per_group", "threads", "lds_bytes")
 
 
 class CmeError(RuntimeError):
@@ -74,9 +77,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cme_adjoint": (ctypes.c_int, [P, P, P, i64, i64, i32, P, P, P, P, P]),
         "cme_status": (ctypes.c_int, [P, P]),
         "cme_set_stream": (ctypes.c_int, [P, P]),
-        "cme_plan_kernel": (ctypes.c_int, [P, i32, P, P, P]),
+        "cme_plan_kernel": (ctypes.c_int, [P, i32, P]),
         "cme_plan_select": (ctypes.c_int, [P, i32, i32]),
         "cme_list_kernels": (ctypes.c_int, [i32, i32, P, i32]),
+        "cme_kernel_info": (ctypes.c_int, [i32, P, i32]),
         "cme_destroy": (ctypes.c_int, [P]),
         "cme_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cme_version": (ctypes.c_int, []),
@@ -179,24 +183,37 @@ def cme_set_stream(plan: int, stream=None) -> None:
     _check(load_library().cme_set_stream(plan, _stream_handle(stream)), "cme_set_stream")
 
 
-def cme_plan_kernel(plan: int, n_modes: int):
-    e, t, ipb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    _check(load_library().cme_plan_kernel(plan, int(n_modes), ctypes.byref(e), ctypes.byref(t),
-                                          ctypes.byref(ipb)), "cme_plan_kernel")
-    return {"elems_per_thread": e.value, "threads_per_instance": t.value,
-            "instances_per_group": ipb.value}
+def cme_plan_kernel(plan: int, n_modes: int) -> int:
+    kid = ctypes.c_int32()
+    _check(load_library().cme_plan_kernel(plan, int(n_modes), ctypes.byref(kid)),
+           "cme_plan_kernel")
+    return kid.value
 
 
-def cme_plan_select(plan: int, n_modes: int, elems_per_thread: int) -> None:
-    _check(load_library().cme_plan_select(plan, int(n_modes), int(elems_per_thread)),
-           "cme_plan_select")
+def cme_plan_select(plan: int, n_modes: int, kernel_id: int) -> None:
+    _check(load_library().cme_plan_select(plan, int(n_modes), int(kernel_id)), "cme_plan_select")
 
 
 def cme_list_kernels(precision: int, n_modes: int) -> list:
-    out = np.zeros(16, dtype=np.int32)
+    out = np.zeros(64, dtype=np.int32)
     k = load_library().cme_list_kernels(int(precision), int(n_modes),
-                                        out.ctypes.data_as(ctypes.c_void_p), 16)
-    return [int(x) for x in out[:min(k, 16)]]
+                                        out.ctypes.data_as(ctypes.c_void_p), 64)
+    return [int(x) for x in out[:min(k, 64)]]
+
+
+def cme_kernel_info(kernel_id: int) -> dict:
+    out = np.zeros(9, dtype=np.int32)
+    rc = load_library().cme_kernel_info(int(kernel_id), out.ctypes.data_as(ctypes.c_void_p), 9)
+    if rc < 0:
+        raise CmeError(rc, "cme_kernel_info")
+    info = dict(zip(KERNEL_INFO_FIELDS, (int(x) for x in out)))
+    info["id"] = int(kernel_id)
+    info["threads_per_instance"] = info["n_modes"] // info["elems_per_thread"]
+    info["name"] = (("rk4_wave" if info["kind"] == 1 else "rk4_persistent")
+                    + "<{},{},{},{},{}>".format("double" if info["precision"] == 0 else "float",
+                                                info["n_modes"], info["elems_per_thread"],
+                                                info["sub_transforms"], info["pad_shift"]))
+    return info
 
 
 def cme_destroy(plan: Optional[int]) -> None:
@@ -257,11 +274,12 @@ class Plan:
     def status(self) -> np.ndarray:
         return cme_status(self.handle, self.batch)
 
-    def kernel(self, n_modes: int):
-        return cme_plan_kernel(self.handle, n_modes)
+    def kernel(self, n_modes: int) -> dict:
+        """Shape of the kernel variant the plan uses for this size."""
+        return cme_kernel_info(cme_plan_kernel(self.handle, n_modes))
 
-    def select(self, n_modes: int, elems_per_thread: int):
-        cme_plan_select(self.handle, n_modes, elems_per_thread)
+    def select(self, n_modes: int, kernel_id: int):
+        cme_plan_select(self.handle, n_modes, kernel_id)
 
     def close(self):
         if getattr(self, "handle", None):

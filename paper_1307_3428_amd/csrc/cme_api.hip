@@ -21,6 +21,22 @@
 using cme::DevInst;
 using cme::Variant;
 
+namespace cme {
+const Variant *variants(int *count) {
+  static const std::vector<Variant> all = [] {
+    std::vector<Variant> v;
+    int n = 0;
+    const Variant *a = variants_wave(&n);
+    v.insert(v.end(), a, a + n);
+    a = variants_team(&n);
+    v.insert(v.end(), a, a + n);
+    return v;
+  }();
+  *count = (int)all.size();
+  return all.data();
+}
+}  // namespace cme
+
 namespace {
 
 struct SizeClass {
@@ -68,30 +84,31 @@ namespace {
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
-// Default elements per thread for each mode count (FP64).
-int default_e(int n) {
-  switch (n) {
-    case 16: case 32: case 64: return 4;
-    case 4096: case 8192: return 16;
-    default: return 8;
-  }
-}
+const Variant *all_variants(int *count) { return cme::variants(count); }
 
-const Variant *find_variant(int precision, int n, int e) {
+// The default kernel for a size is the first compiled variant listed for it
+// (the tables list the preferred shape first).
+const Variant *default_variant(int precision, int n) {
   int cnt = 0;
-  const Variant *v = cme::variants(&cnt);
+  const Variant *v = all_variants(&cnt);
   for (int i = 0; i < cnt; ++i)
-    if (v[i].precision == precision && v[i].n == n && v[i].e == e) return &v[i];
+    if (v[i].precision == precision && v[i].n == n) return &v[i];
   return nullptr;
 }
 
 std::vector<const Variant *> candidates(int precision, int n) {
   int cnt = 0;
-  const Variant *v = cme::variants(&cnt);
+  const Variant *v = all_variants(&cnt);
   std::vector<const Variant *> out;
   for (int i = 0; i < cnt; ++i)
     if (v[i].precision == precision && v[i].n == n) out.push_back(&v[i]);
   return out;
+}
+
+int variant_id(const Variant *x) {
+  int cnt = 0;
+  const Variant *v = all_variants(&cnt);
+  return (int)(x - v);
 }
 
 // Classic RK4 stability polynomial R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24.
@@ -359,14 +376,10 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
     SizeClass c;
     c.n = g.first;
     c.ids = g.second;
-    c.var = find_variant(precision, c.n, default_e(c.n));
+    c.var = default_variant(precision, c.n);
     if (!c.var) {
-      auto cand = candidates(precision, c.n);
-      if (cand.empty()) {
-        rc = CME_EUNSUPPORTED;
-        break;
-      }
-      c.var = cand.front();
+      rc = CME_EUNSUPPORTED;
+      break;
     }
     if (hipMalloc((void **)&c.d_order, sizeof(int32_t) * c.ids.size()) != hipSuccess) {
       rc = CME_ENOMEM;
@@ -479,35 +492,47 @@ int cme_status(cme_plan *p, int32_t *flags) {
   return CME_OK;
 }
 
-int cme_plan_kernel(const cme_plan *p, int32_t n_modes, int32_t *e, int32_t *t, int32_t *ipb) {
-  if (!p) return CME_EINVAL;
+int cme_plan_kernel(const cme_plan *p, int32_t n_modes, int32_t *kernel_id) {
+  if (!p || !kernel_id) return CME_EINVAL;
   for (const auto &c : p->classes) {
     if (c.n != n_modes) continue;
-    if (e) *e = c.var->e;
-    if (t) *t = c.var->n / c.var->e;
-    if (ipb) *ipb = c.var->ipb;
+    *kernel_id = variant_id(c.var);
     return CME_OK;
   }
   return CME_EINVAL;
 }
 
-int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t e) {
+int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t kernel_id) {
   if (!p) return CME_EINVAL;
+  int cnt = 0;
+  const Variant *v = all_variants(&cnt);
   for (auto &c : p->classes) {
     if (c.n != n_modes) continue;
-    const Variant *v = find_variant(p->precision, n_modes, e);
-    if (!v) return CME_EUNSUPPORTED;
-    c.var = v;
+    if (kernel_id < 0 || kernel_id >= cnt || v[kernel_id].n != n_modes ||
+        v[kernel_id].precision != p->precision)
+      return CME_EUNSUPPORTED;
+    c.var = &v[kernel_id];
     return CME_OK;
   }
   return CME_EINVAL;
 }
 
-int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *out, int32_t cap) {
+int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t cap) {
   const auto c = candidates(precision, n_modes);
   for (size_t i = 0; i < c.size() && (int32_t)i < cap; ++i)
-    if (out) out[i] = c[i]->e;
+    if (ids) ids[i] = variant_id(c[i]);
   return (int32_t)c.size();
+}
+
+int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap) {
+  int cnt = 0;
+  const Variant *v = all_variants(&cnt);
+  if (kernel_id < 0 || kernel_id >= cnt || !info || cap < 1) return CME_EINVAL;
+  const Variant &x = v[kernel_id];
+  const int32_t vals[9] = {x.precision, x.n, x.e, x.v, x.ps, x.kind, x.ipb, x.threads,
+                           x.lds_bytes};
+  for (int i = 0; i < 9 && i < cap; ++i) info[i] = vals[i];
+  return 9;
 }
 
 int cme_destroy(cme_plan *p) {

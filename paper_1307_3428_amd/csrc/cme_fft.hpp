@@ -61,6 +61,23 @@ __device__ __forceinline__ cx<Real> ctw(cx<Real> a, cx<Real> w) {
 
 template <int I> using ic = std::integral_constant<int, I>;
 
+// Synchronisation scope of an LDS exchange: the whole workgroup (s_barrier),
+// or one wavefront.  LDS operations of one wavefront execute in program
+// order, so a wave-local exchange needs no barrier instruction; the fences
+// and the wave barrier only keep the compiler from reordering the accesses.
+enum { SYNC_BLOCK = 0, SYNC_WAVE = 1 };
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int SYNC> __device__ __forceinline__ void team_sync() {
+  if constexpr (SYNC == SYNC_BLOCK) __syncthreads();
+  else wave_sync();
+}
+
 // f(ic<B>), f(ic<B+1>), ..., f(ic<E-1>) with compile-time indices
 template <int B, int E, typename F>
 __device__ __forceinline__ void sfor(F &&f) {
@@ -208,8 +225,8 @@ template <int N, int PS> struct LdsLen {
 };
 
 // Load the per-thread twiddles of every pass from the table
-// tab[i] = exp(-2 pi i i / N), i < N.
-template <int N, int E, typename Real>
+// tab[i * TS] = exp(-2 pi i i / N), i < N (TS: stride of a longer table).
+template <int N, int E, int TS = 1, typename Real>
 __device__ __forceinline__ void load_twiddles(cx<Real> (&tw)[(FftPlan<N, E>::NTW)],
                                               const cx<Real> *__restrict__ tab, int t) {
   using PL = FftPlan<N, E>;
@@ -222,7 +239,7 @@ __device__ __forceinline__ void load_twiddles(cx<Real> (&tw)[(FftPlan<N, E>::NTW
       const int k = (t + q * PL::T) & (NSp - 1);
       sfor<1, R>([&](auto ri) {
         constexpr int r = decltype(ri)::value;
-        tw[OFF + q * (R - 1) + (r - 1)] = tab[r * k * STRIDE];
+        tw[OFF + q * (R - 1) + (r - 1)] = tab[r * k * STRIDE * TS];
       });
     });
   });
@@ -231,11 +248,12 @@ __device__ __forceinline__ void load_twiddles(cx<Real> (&tw)[(FftPlan<N, E>::NTW
 // One transform of sign S (S = +1: a_j = sum_m x_m e^{+2 pi i j m / N};
 // S = -1: e^{-...}; no scaling) of the sequence held as v[m] = x[t + m T].
 // LDS: with PING (two buffers) each exchange alternates buffers starting at
-// parity PAR0 and needs one barrier; with a single buffer each exchange is
-// fenced by a barrier on both sides.  Returns the parity after the transform.
-template <int N, int E, int S, int PS, bool PING, int PAR0, typename Real>
-__device__ __forceinline__ void fft_team(cx<Real> (&v)[E], cx<Real> *__restrict__ buf0,
-                                         cx<Real> *__restrict__ buf1,
+// parity PAR0 and needs one synchronisation; with a single buffer each
+// exchange is fenced on both sides.  SYNC selects workgroup or wave scope
+// (a wave-scope team is exactly one wavefront).
+template <int N, int E, int S, int PS, bool PING, int PAR0, int SYNC = SYNC_BLOCK,
+          typename Real>
+__device__ __forceinline__ void fft_team(cx<Real> (&v)[E], cx<Real> *buf0, cx<Real> *buf1,
                                          const cx<Real> (&tw)[(FftPlan<N, E>::NTW)], int t) {
   using PL = FftPlan<N, E>;
   constexpr int T = PL::T;
@@ -255,7 +273,7 @@ __device__ __forceinline__ void fft_team(cx<Real> (&v)[E], cx<Real> *__restrict_
       // single buffer: every thread must be done reading it (in the previous
       // pass, or in the last pass of the previous transform) before it is
       // overwritten
-      __syncthreads();
+      team_sync<SYNC>();
     }
     cx<Real> *dst = (PING && ((PAR0 + p) & 1)) ? buf1 : buf0;
     sfor<0, Q>([&](auto qi) {
@@ -282,10 +300,222 @@ __device__ __forceinline__ void fft_team(cx<Real> (&v)[E], cx<Real> *__restrict_
         });
       }
     });
-    if constexpr (!LAST) __syncthreads();
+    if constexpr (!LAST) team_sync<SYNC>();
   });
 }
 
 template <int N, int E> constexpr int fft_exchanges() { return FftPlan<N, E>::P - 1; }
+
+// ---------------------------------------------------------------------------
+// Two-level transform for a workgroup of W wavefronts (T = 64 W threads),
+// each wavefront running V independent wave-local sub-transforms.
+//
+// N = WV N1 with WV = W V "virtual waves" and N1 = 64 ES (ES = E / V modes
+// per thread per sub-transform).  Index maps n = n1 + N1 n2 (input side) and
+// k = k2 + WV k1 (output side):
+//   X[k2 + WV k1] = sum_n1 e^{s 2pi i n1 k1 / N1} e^{s 2pi i n1 k2 / N}
+//                   sum_n2 x[n1 + N1 n2] e^{s 2pi i n2 k2 / WV}.
+// Forward path (input in mode order, output scrambled):
+//   (a) WV-point DFTs over n2 in registers, (b) twiddles e^{s 2pi i n1 k2/N},
+//   (c) one transpose across waves through LDS (the only workgroup barrier),
+//   then the N1-point transform over n1 for k2 = w V + v, v < V, inside wave
+//   w; its exchanges are wave-local, and the V sub-transforms of a wave are
+//   independent, so the LDS traffic of one overlaps the arithmetic of another.
+// Back path: the mirror image (wave-local N1-point transforms, twiddles,
+// transpose across waves, WV-point DFTs in registers), taking the scrambled
+// order to mode order.  The pointwise cube of Eq. (4) does not care about the
+// order of the transformed field, so an inverse transform on the forward path
+// followed by a forward transform on the back path returns the four-wave-
+// mixing sum in the registers that held the mode amplitudes.
+//
+// Ownership: lane l of wave w holds, in slot m = i + Q n2 (Q = E / WV),
+//   mode n = l + 64 (w Q + i) + N1 n2,
+// and on the scrambled side, in slot m = v ES + j, the element
+//   k = (w V + v) + WV (l + 64 j).
+// ---------------------------------------------------------------------------
+// Synchronisation of the cross-wave exchange: a workgroup barrier, or a wave
+// fence when the whole instance lives in one wavefront (W = 1).
+template <int W> __device__ __forceinline__ void cross_sync() {
+  if constexpr (W == 1) wave_sync();
+  else __syncthreads();
+}
+
+template <int N, int E, int V> struct WavePlan {
+  static constexpr int T = N / E;
+  static constexpr int W = T / 64;
+  static constexpr int ES = E / V;
+  static constexpr int N1 = 64 * ES;
+  static constexpr int WV = W * V;
+  static constexpr int Q = E / WV;
+  using Sub = FftPlan<N1, ES>;
+  static_assert(T % 64 == 0 && W >= 1 && E % V == 0 && E % WV == 0 && WV <= 64,
+                "bad wave plan");
+  static constexpr int NTX = WV > 1 ? Q * (WV - 1) : 1;  // cross twiddles, forward path
+  static constexpr int NTY = WV > 1 ? E : 1;             // cross twiddles, back path
+  __device__ static int mode(int w, int l, int m) {
+    return l + 64 * (w * Q + m % Q) + N1 * (m / Q);
+  }
+};
+
+template <int N, int E, int V, typename Real> struct WaveTwiddles {
+  using WP = WavePlan<N, E, V>;
+  cx<Real> sub[WP::Sub::NTW];
+  cx<Real> x[WP::NTX];
+  cx<Real> y[WP::NTY];
+};
+
+// tab[i] = exp(-2 pi i i / N), i < N
+template <int N, int E, int V, typename Real>
+__device__ __forceinline__ void load_wave_twiddles(WaveTwiddles<N, E, V, Real> &tw,
+                                                   const cx<Real> *__restrict__ tab, int w,
+                                                   int l) {
+  using WP = WavePlan<N, E, V>;
+  load_twiddles<WP::N1, WP::ES, WP::WV>(tw.sub, tab, l);
+  if constexpr (WP::WV > 1) {
+    sfor<0, WP::Q>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      const int n1 = l + 64 * (w * WP::Q + i);
+      sfor<1, WP::WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        tw.x[i * (WP::WV - 1) + r - 1] = tab[n1 * r];
+      });
+    });
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      constexpr int v = m / WP::ES, j = m % WP::ES;
+      tw.y[m] = tab[(l + 64 * j) * (w * V + v)];
+    });
+  }
+}
+
+// V independent wave-local transforms of length N1 = 64 ES, in place in the
+// regions reg + v * LB1.  Each pass first issues the reads of all V
+// sequences, then computes and writes them one after the other, so the reads
+// of sequence v+1 and the writes of sequence v overlap the arithmetic.
+template <int N1, int ES, int V, int S, int PS, typename Real>
+__device__ __forceinline__ void fft_wave_multi(cx<Real> (&v)[V * ES], cx<Real> *reg,
+                                               const cx<Real> (&tw)[(FftPlan<N1, ES>::NTW)],
+                                               int l) {
+  using PL = FftPlan<N1, ES>;
+  constexpr int T = 64;
+  constexpr int LB1 = LdsLen<N1, PS>::value;
+  sfor<0, PL::P>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), NSp = PL::ns(p), QD = PL::qd(p), OFF = PL::twoff(p);
+    constexpr int Qb = ES / R;
+    constexpr bool LAST = p == PL::P - 1;
+    if constexpr (p > 0) {
+      sfor<0, V>([&](auto vi) {
+        constexpr int vv = decltype(vi)::value;
+        sfor<0, ES>([&](auto mi) {
+          constexpr int m = decltype(mi)::value;
+          v[vv * ES + m] = reg[vv * LB1 + lpad<PS>(l + m * T)];
+        });
+      });
+    }
+    if constexpr (!LAST) wave_sync();  // in place: reads before writes
+    sfor<0, V>([&](auto vi) {
+      constexpr int vv = decltype(vi)::value;
+      sfor<0, Qb>([&](auto qi) {
+        constexpr int q = decltype(qi)::value;
+        cx<Real> z[R];
+        sfor<0, R>([&](auto ri) {
+          z[decltype(ri)::value] = v[vv * ES + q + decltype(ri)::value * Qb];
+        });
+        if constexpr (NSp > 1) {
+          constexpr int qq = q % QD;
+          sfor<1, R>([&](auto ri) {
+            constexpr int r = decltype(ri)::value;
+            z[r] = ctw<S>(z[r], tw[OFF + qq * (R - 1) + (r - 1)]);
+          });
+        }
+        dft_reg<R, S>(z);
+        if constexpr (LAST) {
+          sfor<0, R>([&](auto ri) {
+            v[vv * ES + q + decltype(ri)::value * Qb] = z[decltype(ri)::value];
+          });
+        } else {
+          const int j = l + q * T;
+          const int k = j & (NSp - 1);
+          const int base = (j - k) * R + k;
+          sfor<0, R>([&](auto ri) {
+            constexpr int r = decltype(ri)::value;
+            reg[vv * LB1 + lpad<PS>(base + r * NSp)] = z[r];
+          });
+        }
+      });
+    });
+    if constexpr (!LAST) wave_sync();
+  });
+}
+
+// Forward path of sign S.  X: WV regions of LB1 = padded N1 elements.
+// PRE: issue a workgroup barrier before the cross-wave writes (needed when
+// another wave may still be reading X).
+template <int N, int E, int V, int S, int PS, bool PRE, typename Real>
+__device__ __forceinline__ void fft_fwdpath(cx<Real> (&v)[E], cx<Real> *X,
+                                            const WaveTwiddles<N, E, V, Real> &tw, int w, int l) {
+  using WP = WavePlan<N, E, V>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, Q = WP::Q, ES = WP::ES;
+  if constexpr (WV > 1) {
+    if constexpr (PRE) cross_sync<WP::W>();
+    sfor<0, Q>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      cx<Real> z[WV];
+      sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[i + Q * decltype(ri)::value]; });
+      dft_reg<WV, S>(z);
+      const int n1 = l + 64 * (w * Q + i);
+      sfor<1, WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        z[r] = ctw<S>(z[r], tw.x[i * (WV - 1) + r - 1]);
+      });
+      sfor<0, WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        X[r * LB1 + lpad<PS>(n1)] = z[r];
+      });
+    });
+    cross_sync<WP::W>();
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      constexpr int vv = m / ES, j = m % ES;
+      v[m] = X[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)];
+    });
+  }
+  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+}
+
+// Back path of sign S.  The wave-local transforms run in X (own regions); the
+// cross-wave exchange goes through Y (may equal X only if the caller fences
+// the next forward path with PRE).
+template <int N, int E, int V, int S, int PS, typename Real>
+__device__ __forceinline__ void fft_backpath(cx<Real> (&v)[E], cx<Real> *X, cx<Real> *Y,
+                                             const WaveTwiddles<N, E, V, Real> &tw, int w,
+                                             int l) {
+  using WP = WavePlan<N, E, V>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, Q = WP::Q, ES = WP::ES;
+  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  if constexpr (WV > 1) {
+    if (Y == X) wave_sync();  // own regions: the transform's last reads come first
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      constexpr int vv = m / ES, j = m % ES;
+      Y[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)] = ctw<S>(v[m], tw.y[m]);
+    });
+    cross_sync<WP::W>();
+    sfor<0, Q>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      const int n1 = l + 64 * (w * Q + i);
+      cx<Real> z[WV];
+      sfor<0, WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        z[r] = Y[r * LB1 + lpad<PS>(n1)];
+      });
+      dft_reg<WV, S>(z);
+      sfor<0, WV>([&](auto ri) { v[i + Q * decltype(ri)::value] = z[decltype(ri)::value]; });
+    });
+  }
+}
 
 }  // namespace cme

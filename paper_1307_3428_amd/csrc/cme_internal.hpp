@@ -66,11 +66,14 @@ __host__ __device__ inline double sigma_at(double sigma0, double sigma1, double 
 using FwdLaunch = hipError_t (*)(const RunArgs &, hipStream_t);
 using AdjLaunch = hipError_t (*)(const AdjArgs &, hipStream_t);
 
-// One compiled kernel variant for a (precision, N, elements-per-thread) triple.
+// One compiled kernel variant.
 struct Variant {
   int precision;   // 0 FP64, 1 FP32
   int n;           // modes
   int e;           // elements per thread
+  int v;           // wave-local sub-transforms per wave (1 for team kernels)
+  int ps;          // LDS padding: one element every 2^ps (0: none)
+  int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -78,6 +81,8 @@ struct Variant {
   AdjLaunch adj;   // null if no adjoint kernel for this variant
 };
 
-const Variant *variants(int *count);
+const Variant *variants_team(int *count);  // cme_kernels.hip
+const Variant *variants_wave(int *count);  // cme_wave.hip
+const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 }  // namespace cme

@@ -284,20 +284,19 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t st) {
 
 #define CME_PS(E) (ilog2(E))
 #define CME_V64(N, E)                                                                       \
-  Variant{0, N, E, KernelShape<double, N, E, CME_PS(E)>::IPB,                               \
+  Variant{0, N, E, 1, CME_PS(E), 0, KernelShape<double, N, E, CME_PS(E)>::IPB,              \
           KernelShape<double, N, E, CME_PS(E)>::THREADS,                                    \
           KernelShape<double, N, E, CME_PS(E)>::LDS_BYTES, &launch_fwd<double, N, E, CME_PS(E)>, \
           &launch_adj<double, N, E, CME_PS(E)>}
 
+// Team kernels cover the sizes where one instance is smaller than a
+// wavefront's worth of threads (several instances share a wavefront).
 static const Variant kVariants[] = {
-    CME_V64(16, 4),   CME_V64(32, 4),   CME_V64(64, 4),    CME_V64(64, 8),
-    CME_V64(128, 4),  CME_V64(128, 8),  CME_V64(256, 4),   CME_V64(256, 8),
-    CME_V64(512, 4),  CME_V64(512, 8),  CME_V64(1024, 4),  CME_V64(1024, 8),
-    CME_V64(1024, 16), CME_V64(2048, 4), CME_V64(2048, 8), CME_V64(2048, 16),
-    CME_V64(4096, 8), CME_V64(4096, 16), CME_V64(8192, 8), CME_V64(8192, 16),
+    CME_V64(16, 4),  CME_V64(32, 4),  CME_V64(64, 4),  CME_V64(64, 8),
+    CME_V64(128, 4), CME_V64(128, 8), CME_V64(256, 8),
 };
 
-const Variant *variants(int *count) {
+const Variant *variants_team(int *count) {
   *count = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
   return kVariants;
 }

@@ -44,12 +44,23 @@ def test_strerror_and_version():
 
 
 def test_kernel_table_covers_every_size():
+    seen = set()
     for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
-        es = C.cme_list_kernels(C.CME_F64, n)
-        assert es, n
-        for e in es:
+        ids = C.cme_list_kernels(C.CME_F64, n)
+        assert ids, n
+        for k in ids:
+            info = C.cme_kernel_info(k)
+            assert info["n_modes"] == n and info["precision"] == C.CME_F64
+            e = info["elems_per_thread"]
             assert e & (e - 1) == 0 and 2 <= e <= n
+            assert info["threads"] == info["instances_per_group"] * (n // e)
+            assert info["threads"] <= 1024 and info["lds_bytes"] <= 160 * 1024
+            if info["kind"] == 1:     # two-level kernels: whole wavefronts per instance
+                assert (n // e) % 64 == 0
+            seen.add(k)
     assert C.cme_list_kernels(C.CME_F64, 100) == []
+    with pytest.raises(C.CmeError):
+        C.cme_kernel_info(10 ** 6)
 
 
 def _inst(n=64, offset=0, **kw):
@@ -126,7 +137,7 @@ def test_calls_on_null_plan():
     flags = np.zeros(1, np.int32)
     assert lib.cme_status(None, flags.ctypes.data_as(ctypes.c_void_p)) == C.CME_EINVAL
     assert lib.cme_destroy(None) == C.CME_OK
-    assert lib.cme_plan_kernel(None, 64, None, None, None) == C.CME_EINVAL
+    assert lib.cme_plan_kernel(None, 64, None) == C.CME_EINVAL
     assert lib.cme_plan_select(None, 64, 4) == C.CME_EINVAL
     assert lib.cme_set_stream(None, None) == C.CME_EINVAL
 

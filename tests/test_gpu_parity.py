@@ -35,11 +35,11 @@ def per_instance_err(packed, y_gpu, y_orc):
     return [rel_err(y_gpu[packed.slice(b)], y_orc[packed.slice(b)]) for b in range(packed.batch)]
 
 
-def gpu_run(C, packed, h, steps, step0=0, e=None, n=None, flags=0):
+def gpu_run(C, packed, h, steps, step0=0, kid=None, n=None, flags=0):
     import torch
     with C.Plan(packed, h, flags=flags) as plan:
-        if e is not None:
-            plan.select(n, e)
+        if kid is not None:
+            plan.select(n, kid)
         A = plan.state(packed.a0)
         plan.run(A, steps, step0=step0)
         torch.cuda.synchronize()
@@ -58,34 +58,26 @@ def moderate_batch(seed, sizes):
     return insts
 
 
-def _variants():
-    from paper_1307_3428_amd import cme as C
-    out = []
-    for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
-        try:
-            es = C.cme_list_kernels(C.CME_F64, n)
-        except RuntimeError:
-            es = []
-        for e in es:
-            out.append((n, e))
-    return out
-
-
 def _variant_params():
+    """(N, kernel id) for every compiled FP64 variant (ids are stable for a
+    given build: the order of the kernel tables)."""
     try:
-        return _variants()
+        from paper_1307_3428_amd import cme as C
+        return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
+                for k in C.cme_list_kernels(C.CME_F64, n)]
     except Exception:
-        return [(16, 4)]
+        return [(16, 0)]
 
 
-@pytest.mark.parametrize("n,e", _variant_params())
-def test_each_kernel_variant_matches_oracle(cme, orc, n, e):
-    print(f"variant N={n} E={e}", flush=True)
-    batch = 3 if n <= 1024 else 2
-    insts = moderate_batch(1000 + n + e, [n] * batch)
+@pytest.mark.parametrize("n,kid", _variant_params())
+def test_each_kernel_variant_matches_oracle(cme, orc, n, kid):
+    info = cme.cme_kernel_info(kid)
+    print(f"variant {info['name']}", flush=True)
+    batch = 5 if info["instances_per_group"] > 1 else 2
+    insts = moderate_batch(1000 + n + kid, [n] * batch)
     p = W.pack(insts)
     steps, h = 4, 0.01
-    y, st = gpu_run(cme, p, h, steps, step0=5, e=e, n=n)
+    y, st = gpu_run(cme, p, h, steps, step0=5, kid=kid, n=n)
     ref, _ = orc.run(p, h, steps, step0=5)
     errs = per_instance_err(p, y, ref)
     assert max(errs) <= 1e-13, errs
