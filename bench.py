@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "mode-steps/s (FP64, 1 GPU) at ≤1e-10 rel. error vs oracle; adjoint/forward ratio"
 FP64_PEAK_TFLOPS = 78.6
-COUNTERS = os.path.join(ROOT, "profiles", "rk4_persistent_sweep_n2048_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "rk4_wave_sweep_n2048_counters.txt")
 KERNEL_SOURCES = ("cme_fft.hpp", "cme_kernels.hip", "cme_wave.hip", "cme_internal.hpp")
 
 
@@ -45,9 +45,12 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_launch_units: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if there is none or the kernel sources changed since."""
+def read_traffic():
+    """HBM bytes of one launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads for a
+    1 GiB copy), or None if there is none or the kernel sources changed since.
+    The state stays on chip for the whole run, so the bytes of a launch do not
+    depend on how many RK4 steps it takes."""
     if not os.path.exists(COUNTERS):
         return None
     vals = {}
@@ -61,10 +64,9 @@ def read_traffic(n_launch_units: int):
     try:
         fetch = float(vals["fetch_kib_per_dispatch_scaled"]) * 1024.0
         write = float(vals["write_kib_per_dispatch_scaled"]) * 1024.0
-        units = float(vals["rk4_steps_per_dispatch"])
     except (KeyError, ValueError):
         return None
-    return (fetch + write) * (n_launch_units / units)
+    return fetch + write
 
 
 def counted_flops_per_step(n: int) -> float:
@@ -172,7 +174,7 @@ def main() -> int:
     achieved = flops_per_launch / mean_launch_s / 1e12
     finite = not plan.status().any() and not flags_out.any()
 
-    traffic = read_traffic(p.batch * rk_steps)
+    traffic = read_traffic()
     out = {
         "metric": METRIC,
         "value": value,
