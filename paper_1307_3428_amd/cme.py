@@ -33,7 +33,7 @@ EXPORTED = (
 )
 
 KERNEL_INFO_FIELDS = ("precision", "n_modes", "elems_per_thread", "sub_transforms", "pad_shift",
-                      "kind", "instances_per_group", "threads", "lds_bytes")
+                      "kind", "instances_per_group", "threads", "lds_bytes", "exchange")
 
 
 class CmeError(RuntimeError):
@@ -202,17 +202,19 @@ def cme_list_kernels(precision: int, n_modes: int) -> list:
 
 
 def cme_kernel_info(kernel_id: int) -> dict:
-    out = np.zeros(9, dtype=np.int32)
-    rc = load_library().cme_kernel_info(int(kernel_id), out.ctypes.data_as(ctypes.c_void_p), 9)
+    out = np.zeros(len(KERNEL_INFO_FIELDS), dtype=np.int32)
+    rc = load_library().cme_kernel_info(int(kernel_id), out.ctypes.data_as(ctypes.c_void_p),
+                                        len(KERNEL_INFO_FIELDS))
     if rc < 0:
         raise CmeError(rc, "cme_kernel_info")
     info = dict(zip(KERNEL_INFO_FIELDS, (int(x) for x in out)))
     info["id"] = int(kernel_id)
     info["threads_per_instance"] = info["n_modes"] // info["elems_per_thread"]
-    info["name"] = (("rk4_wave" if info["kind"] == 1 else "rk4_persistent")
-                    + "<{},{},{},{},{}>".format("double" if info["precision"] == 0 else "float",
-                                                info["n_modes"], info["elems_per_thread"],
-                                                info["sub_transforms"], info["pad_shift"]))
+    info["name"] = ({0: "rk4_persistent", 1: "rk4_wave", 2: "rk4_dual"}[info["kind"]]
+                    + "<{},{},{},{},{}{}>".format(
+                        "double" if info["precision"] == 0 else "float", info["n_modes"],
+                        info["elems_per_thread"], info["sub_transforms"], info["pad_shift"],
+                        "," + str(info["exchange"]) if info["kind"] >= 1 else ""))
     return info
 
 

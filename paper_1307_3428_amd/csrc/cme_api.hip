@@ -28,6 +28,8 @@ const Variant *variants(int *count) {
     int n = 0;
     const Variant *a = variants_wave(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_dual(&n);
+    v.insert(v.end(), a, a + n);
     a = variants_team(&n);
     v.insert(v.end(), a, a + n);
     return v;
@@ -529,10 +531,10 @@ int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap) {
   const Variant *v = all_variants(&cnt);
   if (kernel_id < 0 || kernel_id >= cnt || !info || cap < 1) return CME_EINVAL;
   const Variant &x = v[kernel_id];
-  const int32_t vals[9] = {x.precision, x.n, x.e, x.v, x.ps, x.kind, x.ipb, x.threads,
-                           x.lds_bytes};
-  for (int i = 0; i < 9 && i < cap; ++i) info[i] = vals[i];
-  return 9;
+  const int32_t vals[10] = {x.precision, x.n, x.e, x.v, x.ps, x.kind, x.ipb, x.threads,
+                            x.lds_bytes, x.tp};
+  for (int i = 0; i < 10 && i < cap; ++i) info[i] = vals[i];
+  return 10;
 }
 
 int cme_destroy(cme_plan *p) {

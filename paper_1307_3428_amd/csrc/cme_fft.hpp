@@ -333,6 +333,163 @@ template <int N, int E> constexpr int fft_exchanges() { return FftPlan<N, E>::P 
 // and on the scrambled side, in slot m = v ES + j, the element
 //   k = (w V + v) + WV (l + 64 j).
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Register transposes between the slots a thread holds and its lane bits.
+//
+// xpose<C>(a, b): for a pair of register slots (a: slot bit 0, b: slot bit 1)
+// exchange that slot bit with lane bit C, i.e. afterwards lane l holds in
+// slot bit s the value lane (l with bit C := s) held in slot bit (l's bit C).
+// Lane bits 5 and 4 use v_permlane32_swap / v_permlane16_swap (one
+// instruction per 32-bit word pair), bits 3 and 2 DPP row rotations with
+// bank masks (two), bits 1 and 0 DPP quad permutes plus a select (four).
+// No LDS is involved.
+// ---------------------------------------------------------------------------
+template <int C> __device__ __forceinline__ void xpose_u32(uint32_t &a, uint32_t &b, int lane) {
+  if constexpr (C == 5) {
+    auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else if constexpr (C == 4) {
+    auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    a = r[0];
+    b = r[1];
+  } else if constexpr (C == 3) {
+    // partner = lane ^ 8 = rotation by 8 inside a row of 16; banks 2,3 hold bit 3 set
+    const uint32_t na = __builtin_amdgcn_update_dpp(a, b, 0x128, 0xF, 0xC, false);
+    const uint32_t nb = __builtin_amdgcn_update_dpp(b, a, 0x128, 0xF, 0x3, false);
+    a = na;
+    b = nb;
+  } else if constexpr (C == 2) {
+    // lanes with bit 2 set (banks 1, 3) take from lane - 4 (row_ror:4), the
+    // others from lane + 4 (row_ror:12)
+    const uint32_t na = __builtin_amdgcn_update_dpp(a, b, 0x124, 0xF, 0xA, false);
+    const uint32_t nb = __builtin_amdgcn_update_dpp(b, a, 0x12C, 0xF, 0x5, false);
+    a = na;
+    b = nb;
+  } else {
+    // quad_perm [2,3,0,1] (lane ^ 2) or [1,0,3,2] (lane ^ 1)
+    constexpr int QP = C == 1 ? 0x4E : 0xB1;
+    const uint32_t pb = __builtin_amdgcn_mov_dpp(b, QP, 0xF, 0xF, false);
+    const uint32_t pa = __builtin_amdgcn_mov_dpp(a, QP, 0xF, 0xF, false);
+    const bool hi = (lane >> C) & 1;
+    const uint32_t na = hi ? pb : a, nb = hi ? b : pa;
+    a = na;
+    b = nb;
+  }
+}
+
+template <int C, typename Real>
+__device__ __forceinline__ void xpose(cx<Real> &a, cx<Real> &b, int lane) {
+  constexpr int NW = (int)(sizeof(cx<Real>) / 4);
+  uint32_t wa[NW], wb[NW];
+  __builtin_memcpy(wa, &a, sizeof(a));
+  __builtin_memcpy(wb, &b, sizeof(b));
+  sfor<0, NW>([&](auto di) { xpose_u32<C>(wa[decltype(di)::value], wb[decltype(di)::value], lane); });
+  __builtin_memcpy(&a, wa, sizeof(a));
+  __builtin_memcpy(&b, wb, sizeof(b));
+}
+
+// Exchange the three slot bits of v[0..7] with lane bits C0+2, C0+1, C0:
+// afterwards slot = old (lane >> C0) & 7 and (lane >> C0) & 7 = old slot.
+template <int C0, typename Real>
+__device__ __forceinline__ void xpose8(cx<Real> *v, int lane) {
+  sfor<0, 4>([&](auto si) {
+    constexpr int s = decltype(si)::value;
+    xpose<C0 + 2>(v[s], v[s + 4], lane);
+  });
+  sfor<0, 4>([&](auto si) {
+    constexpr int s = (decltype(si)::value & 1) + 4 * (decltype(si)::value >> 1);
+    xpose<C0 + 1>(v[s], v[s + 2], lane);
+  });
+  sfor<0, 4>([&](auto si) {
+    constexpr int s = 2 * decltype(si)::value;
+    xpose<C0>(v[s], v[s + 1], lane);
+  });
+}
+
+// Exchange slot bits with lane bits 0..2 through the wave's LDS region
+// (padded one element in 8): lane l, slot s -> lane (l & 56) | s, slot l & 7.
+template <typename Real>
+__device__ __forceinline__ void xpose8_lo_lds(cx<Real> *v, cx<Real> *reg, int lane) {
+  wave_sync();  // earlier reads of the region come first
+  sfor<0, 8>([&](auto si) {
+    constexpr int s = decltype(si)::value;
+    reg[lpad<3>(8 * (lane & 56) + 8 * s + (lane & 7))] = v[s];
+  });
+  wave_sync();
+  sfor<0, 8>([&](auto si) {
+    constexpr int s = decltype(si)::value;
+    v[s] = reg[lpad<3>(8 * lane + s)];
+  });
+}
+
+// 512-point transforms on one wavefront (64 lanes x 8 slots), three radix-8
+// passes over the slots with register/LDS transposes in between.  With digits
+// n = n0 + 8 n1 + 64 n2 (n0 = lane & 7, n1 = lane >> 3, n2 = slot):
+//   X[k0 + 8 k1 + 64 k2] = sum_n0 w512^{n0 k0} w64^{n0 k1} w8^{n0 k2}
+//                          sum_n1 w64^{n1 k0} w8^{n1 k1} sum_n2 w8^{n2 k0} x[n]
+// (w_M = e^{s 2pi i / M}).  Forward path: natural order in (lane l, slot s
+// holds element l + 64 s), digit-permuted order out (lane l, slot s holds
+// element (l >> 3) + 8 (l & 7) + 64 s).  Back path: the mirror image.
+// Twiddles per lane (s = 1..7): A = w512^{l s}, B = w64^{(l & 7) s},
+// C = w512^{(8 (l & 7) + (l >> 3)) s}, D = w64^{(l >> 3) s}, stored as
+// e^{-2 pi i .} and conjugated by ctw for s = +1.
+template <typename Real> struct Tw512 {
+  cx<Real> a[7], b[7], c[7], d[7];
+};
+
+// tab[i * TS] = exp(-2 pi i i / 512)
+template <int TS, typename Real>
+__device__ __forceinline__ void load_tw512(Tw512<Real> &t, const cx<Real> *__restrict__ tab,
+                                           int lane) {
+  const int lo = lane & 7, hi = lane >> 3, sw = 8 * lo + hi;
+  sfor<1, 8>([&](auto si) {
+    constexpr int s = decltype(si)::value;
+    t.a[s - 1] = tab[(lane * s) * TS];
+    t.b[s - 1] = tab[(8 * lo * s) * TS];
+    t.c[s - 1] = tab[(sw * s) * TS];
+    t.d[s - 1] = tab[(8 * hi * s) * TS];
+  });
+}
+
+template <int S, typename Real>
+__device__ __forceinline__ void twiddle7(cx<Real> *v, const cx<Real> (&w)[7]) {
+  sfor<1, 8>([&](auto si) {
+    constexpr int s = decltype(si)::value;
+    v[s] = ctw<S>(v[s], w[s - 1]);
+  });
+}
+
+// LO_LDS: exchange lane bits 0..2 through LDS (one store + one load per
+// element) instead of DPP (about four instructions per 32-bit word).
+template <int S, bool LO_LDS, typename Real>
+__device__ __forceinline__ void fft512_fwd(cx<Real> *v, cx<Real> *reg, const Tw512<Real> &t,
+                                           int lane) {
+  cx<Real>(&z)[8] = *reinterpret_cast<cx<Real>(*)[8]>(v);
+  dft_reg<8, S>(z);
+  twiddle7<S>(v, t.a);
+  xpose8<3>(v, lane);
+  dft_reg<8, S>(z);
+  twiddle7<S>(v, t.b);
+  if constexpr (LO_LDS) xpose8_lo_lds(v, reg, lane);
+  else xpose8<0>(v, lane);
+  dft_reg<8, S>(z);
+}
+
+template <int S, bool LO_LDS, typename Real>
+__device__ __forceinline__ void fft512_back(cx<Real> *v, cx<Real> *reg, const Tw512<Real> &t,
+                                            int lane) {
+  cx<Real>(&z)[8] = *reinterpret_cast<cx<Real>(*)[8]>(v);
+  dft_reg<8, S>(z);
+  twiddle7<S>(v, t.c);
+  if constexpr (LO_LDS) xpose8_lo_lds(v, reg, lane);
+  else xpose8<0>(v, lane);
+  dft_reg<8, S>(z);
+  twiddle7<S>(v, t.d);
+  xpose8<3>(v, lane);
+  dft_reg<8, S>(z);
+}
+
 // Synchronisation of the cross-wave exchange: a workgroup barrier, or a wave
 // fence when the whole instance lives in one wavefront (W = 1).
 template <int W> __device__ __forceinline__ void cross_sync() {
@@ -340,7 +497,8 @@ template <int W> __device__ __forceinline__ void cross_sync() {
   else __syncthreads();
 }
 
-template <int N, int E, int V> struct WavePlan {
+template <int N, int E, int V, int TP = 0> struct WavePlan {
+  static constexpr int TPOL = TP;  // 0: Stockham sub-transforms; 1, 2: fft512 (1: low bits via LDS)
   static constexpr int T = N / E;
   static constexpr int W = T / 64;
   static constexpr int ES = E / V;
@@ -350,6 +508,7 @@ template <int N, int E, int V> struct WavePlan {
   using Sub = FftPlan<N1, ES>;
   static_assert(T % 64 == 0 && W >= 1 && E % V == 0 && E % WV == 0 && WV <= 64,
                 "bad wave plan");
+  static_assert(TP == 0 || ES == 8, "register-transpose sub-transforms need 8 modes per thread");
   static constexpr int NTX = WV > 1 ? Q * (WV - 1) : 1;  // cross twiddles, forward path
   static constexpr int NTY = WV > 1 ? E : 1;             // cross twiddles, back path
   __device__ static int mode(int w, int l, int m) {
@@ -357,20 +516,22 @@ template <int N, int E, int V> struct WavePlan {
   }
 };
 
-template <int N, int E, int V, typename Real> struct WaveTwiddles {
-  using WP = WavePlan<N, E, V>;
-  cx<Real> sub[WP::Sub::NTW];
+template <int N, int E, int V, int TP, typename Real> struct WaveTwiddles {
+  using WP = WavePlan<N, E, V, TP>;
+  cx<Real> sub[TP == 0 ? WP::Sub::NTW : 1];
+  Tw512<Real> t512;  // used when TP > 0 (the optimiser drops it otherwise)
   cx<Real> x[WP::NTX];
   cx<Real> y[WP::NTY];
 };
 
 // tab[i] = exp(-2 pi i i / N), i < N
-template <int N, int E, int V, typename Real>
-__device__ __forceinline__ void load_wave_twiddles(WaveTwiddles<N, E, V, Real> &tw,
+template <int N, int E, int V, int TP, typename Real>
+__device__ __forceinline__ void load_wave_twiddles(WaveTwiddles<N, E, V, TP, Real> &tw,
                                                    const cx<Real> *__restrict__ tab, int w,
                                                    int l) {
-  using WP = WavePlan<N, E, V>;
-  load_twiddles<WP::N1, WP::ES, WP::WV>(tw.sub, tab, l);
+  using WP = WavePlan<N, E, V, TP>;
+  if constexpr (TP == 0) load_twiddles<WP::N1, WP::ES, WP::WV>(tw.sub, tab, l);
+  else load_tw512<N / 512>(tw.t512, tab, l);
   if constexpr (WP::WV > 1) {
     sfor<0, WP::Q>([&](auto ii) {
       constexpr int i = decltype(ii)::value;
@@ -449,13 +610,123 @@ __device__ __forceinline__ void fft_wave_multi(cx<Real> (&v)[V * ES], cx<Real> *
   });
 }
 
+// ---------------------------------------------------------------------------
+// The two-level transforms split at their workgroup barrier, so that two
+// independent transforms can share one barrier and interleave their work:
+//   forward path = fwd_phase1, barrier, fwd_phase2;
+//   back path    = back_phase1, barrier, back_phase2.
+// Each transform uses one context X of WV regions (LB1 elements each): the
+// forward path writes all regions before the barrier and then works in its
+// own regions; the back path works and writes in its own regions before the
+// barrier and reads all regions after it.  A caller that reuses a context
+// must put another barrier between the last reads of one use and the first
+// writes of the next.
+// ---------------------------------------------------------------------------
+template <int N, int E, int V, int TP, int S, int PS, typename Real>
+__device__ __forceinline__ void fwd_phase1(cx<Real> (&v)[E], cx<Real> *X,
+                                           const WaveTwiddles<N, E, V, TP, Real> &tw, int w,
+                                           int l) {
+  using WP = WavePlan<N, E, V, TP>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, Q = WP::Q;
+  if constexpr (WV > 1) {
+    sfor<0, Q>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      cx<Real> z[WV];
+      sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[i + Q * decltype(ri)::value]; });
+      dft_reg<WV, S>(z);
+      const int n1 = l + 64 * (w * Q + i);
+      sfor<1, WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        z[r] = ctw<S>(z[r], tw.x[i * (WV - 1) + r - 1]);
+      });
+      sfor<0, WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        X[r * LB1 + lpad<PS>(n1)] = z[r];
+      });
+    });
+  }
+}
+
+template <int N, int E, int V, int TP, int S, int PS, typename Real>
+__device__ __forceinline__ void fwd_phase2(cx<Real> (&v)[E], cx<Real> *X,
+                                           const WaveTwiddles<N, E, V, TP, Real> &tw, int w,
+                                           int l) {
+  using WP = WavePlan<N, E, V, TP>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, ES = WP::ES;
+  if constexpr (WV > 1) {
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      constexpr int vv = m / ES, j = m % ES;
+      v[m] = X[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)];
+    });
+  }
+  if constexpr (TP == 0) {
+    fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  } else {
+    sfor<0, V>([&](auto vi) {
+      constexpr int vv = decltype(vi)::value;
+      fft512_fwd<S, TP == 1>(v + vv * 8, X + (w * V + vv) * LB1, tw.t512, l);
+    });
+  }
+}
+
+template <int N, int E, int V, int TP, int S, int PS, typename Real>
+__device__ __forceinline__ void back_phase1(cx<Real> (&v)[E], cx<Real> *X,
+                                            const WaveTwiddles<N, E, V, TP, Real> &tw, int w,
+                                            int l) {
+  using WP = WavePlan<N, E, V, TP>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, ES = WP::ES;
+  if constexpr (TP == 0) {
+    fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  } else {
+    sfor<0, V>([&](auto vi) {
+      constexpr int vv = decltype(vi)::value;
+      fft512_back<S, TP == 1>(v + vv * 8, X + (w * V + vv) * LB1, tw.t512, l);
+    });
+  }
+  if constexpr (WV > 1) {
+    wave_sync();  // the transform's last reads of the region come first
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      constexpr int vv = m / ES, j = m % ES;
+      X[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)] = ctw<S>(v[m], tw.y[m]);
+    });
+  }
+}
+
+template <int N, int E, int V, int TP, int S, int PS, typename Real>
+__device__ __forceinline__ void back_phase2(cx<Real> (&v)[E], cx<Real> *X,
+                                            const WaveTwiddles<N, E, V, TP, Real> &tw, int w,
+                                            int l) {
+  using WP = WavePlan<N, E, V, TP>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, Q = WP::Q;
+  if constexpr (WV > 1) {
+    sfor<0, Q>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      const int n1 = l + 64 * (w * Q + i);
+      cx<Real> z[WV];
+      sfor<0, WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        z[r] = X[r * LB1 + lpad<PS>(n1)];
+      });
+      dft_reg<WV, S>(z);
+      sfor<0, WV>([&](auto ri) { v[i + Q * decltype(ri)::value] = z[decltype(ri)::value]; });
+    });
+  }
+}
+
 // Forward path of sign S.  X: WV regions of LB1 = padded N1 elements.
 // PRE: issue a workgroup barrier before the cross-wave writes (needed when
 // another wave may still be reading X).
-template <int N, int E, int V, int S, int PS, bool PRE, typename Real>
+template <int N, int E, int V, int TP, int S, int PS, bool PRE, typename Real>
 __device__ __forceinline__ void fft_fwdpath(cx<Real> (&v)[E], cx<Real> *X,
-                                            const WaveTwiddles<N, E, V, Real> &tw, int w, int l) {
-  using WP = WavePlan<N, E, V>;
+                                            const WaveTwiddles<N, E, V, TP, Real> &tw, int w,
+                                            int l) {
+  using WP = WavePlan<N, E, V, TP>;
   constexpr int LB1 = LdsLen<WP::N1, PS>::value;
   constexpr int WV = WP::WV, Q = WP::Q, ES = WP::ES;
   if constexpr (WV > 1) {
@@ -482,20 +753,34 @@ __device__ __forceinline__ void fft_fwdpath(cx<Real> (&v)[E], cx<Real> *X,
       v[m] = X[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)];
     });
   }
-  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  if constexpr (TP == 0) {
+    fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  } else {
+    sfor<0, V>([&](auto vi) {
+      constexpr int vv = decltype(vi)::value;
+      fft512_fwd<S, TP == 1>(v + vv * 8, X + (w * V + vv) * LB1, tw.t512, l);
+    });
+  }
 }
 
 // Back path of sign S.  The wave-local transforms run in X (own regions); the
 // cross-wave exchange goes through Y (may equal X only if the caller fences
 // the next forward path with PRE).
-template <int N, int E, int V, int S, int PS, typename Real>
+template <int N, int E, int V, int TP, int S, int PS, typename Real>
 __device__ __forceinline__ void fft_backpath(cx<Real> (&v)[E], cx<Real> *X, cx<Real> *Y,
-                                             const WaveTwiddles<N, E, V, Real> &tw, int w,
+                                             const WaveTwiddles<N, E, V, TP, Real> &tw, int w,
                                              int l) {
-  using WP = WavePlan<N, E, V>;
+  using WP = WavePlan<N, E, V, TP>;
   constexpr int LB1 = LdsLen<WP::N1, PS>::value;
   constexpr int WV = WP::WV, Q = WP::Q, ES = WP::ES;
-  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  if constexpr (TP == 0) {
+    fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  } else {
+    sfor<0, V>([&](auto vi) {
+      constexpr int vv = decltype(vi)::value;
+      fft512_back<S, TP == 1>(v + vv * 8, X + (w * V + vv) * LB1, tw.t512, l);
+    });
+  }
   if constexpr (WV > 1) {
     if (Y == X) wave_sync();  // own regions: the transform's last reads come first
     sfor<0, E>([&](auto mi) {

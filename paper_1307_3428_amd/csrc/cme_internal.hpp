@@ -73,7 +73,9 @@ struct Variant {
   int e;           // elements per thread
   int v;           // wave-local sub-transforms per wave (1 for team kernels)
   int ps;          // LDS padding: one element every 2^ps (0: none)
-  int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel
+  int tp;          // wave kernels: sub-transform kind (0 Stockham, 1 registers + LDS, 2 registers)
+  int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel,
+                   // 2: two-level kernel with two transform chains (cme_dual.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -83,6 +85,7 @@ struct Variant {
 
 const Variant *variants_team(int *count);  // cme_kernels.hip
 const Variant *variants_wave(int *count);  // cme_wave.hip
+const Variant *variants_dual(int *count);  // cme_dual.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 }  // namespace cme

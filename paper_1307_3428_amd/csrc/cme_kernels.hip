@@ -284,7 +284,7 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t st) {
 
 #define CME_PS(E) (ilog2(E))
 #define CME_V64(N, E)                                                                       \
-  Variant{0, N, E, 1, CME_PS(E), 0, KernelShape<double, N, E, CME_PS(E)>::IPB,              \
+  Variant{0, N, E, 1, CME_PS(E), 0, 0, KernelShape<double, N, E, CME_PS(E)>::IPB,              \
           KernelShape<double, N, E, CME_PS(E)>::THREADS,                                    \
           KernelShape<double, N, E, CME_PS(E)>::LDS_BYTES, &launch_fwd<double, N, E, CME_PS(E)>, \
           &launch_adj<double, N, E, CME_PS(E)>}

@@ -20,8 +20,8 @@ __device__ constexpr double kWrw[4] = {1.0, 2.0, 2.0, 1.0};
 __device__ constexpr double kWbw[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
 }  // namespace
 
-template <typename Real, int N, int E, int V, int PS> struct WaveShape {
-  using WP = WavePlan<N, E, V>;
+template <typename Real, int N, int E, int V, int PS, int TP> struct WaveShape {
+  using WP = WavePlan<N, E, V, TP>;
   static constexpr int W = WP::W;
   static constexpr int WV = WP::WV;
   static constexpr int IPB = W == 1 ? 4 : 1;
@@ -34,12 +34,13 @@ template <typename Real, int N, int E, int V, int PS> struct WaveShape {
   static constexpr int THREADS = IPB * WP::T;
   static_assert(LDS_BYTES <= LIMIT, "LDS over the gfx950 per-workgroup limit");
   static_assert(THREADS <= 1024, "workgroup too large");
+  static_assert(TP == 0 || PS == 3, "register-transpose sub-transforms use the 1-in-8 padded region");
 };
 
-template <typename Real, int N, int E, int V, int PS>
-__global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_wave(RunArgs a) {
-  using SH = WaveShape<Real, N, E, V, PS>;
-  using WP = WavePlan<N, E, V>;
+template <typename Real, int N, int E, int V, int PS, int TP>
+__global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) rk4_wave(RunArgs a) {
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  using WP = WavePlan<N, E, V, TP>;
   constexpr int W = WP::W;
   __shared__ cx<Real> lds[SH::IPB * SH::PER_INST];
 
@@ -59,7 +60,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
   const double *kap = a.kappa + d.offset;
   const double *omg = a.omega + d.offset;
 
-  WaveTwiddles<N, E, V, Real> tw;
+  WaveTwiddles<N, E, V, TP, Real> tw;
   load_wave_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> y[E], k[E], acc[E], v[E];
@@ -100,13 +101,13 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
           st[WP::mode(w, lane, m)] = v[m];
         });
       }
-      fft_fwdpath<N, E, V, +1, PS, !SH::TWO>(v, X, tw, w, lane);
+      fft_fwdpath<N, E, V, TP, +1, PS, !SH::TWO>(v, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
         v[m] = {p * v[m].re, p * v[m].im};
       });
-      fft_backpath<N, E, V, -1, PS>(v, X, Y, tw, w, lane);
+      fft_backpath<N, E, V, TP, -1, PS>(v, X, Y, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         cx<Real> u;
@@ -150,10 +151,10 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS>
-__global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_wave_reverse(AdjArgs a) {
-  using SH = WaveShape<Real, N, E, V, PS>;
-  using WP = WavePlan<N, E, V>;
+template <typename Real, int N, int E, int V, int PS, int TP>
+__global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) rk4_wave_reverse(AdjArgs a) {
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  using WP = WavePlan<N, E, V, TP>;
   constexpr int W = WP::W;
   __shared__ cx<Real> lds[SH::IPB * SH::PER_INST];
 
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
   cx<Real> *gA = reinterpret_cast<cx<Real> *>(a.gA) + d.offset;
   const cx<Real> *stages = reinterpret_cast<const cx<Real> *>(a.stages);
 
-  WaveTwiddles<N, E, V, Real> tw;
+  WaveTwiddles<N, E, V, TP, Real> tw;
   load_wave_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> yb1[E], yb[E], ub[E], z[E], fa[E];
@@ -210,12 +211,12 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
         z[m] = {gn * kv.im, -gn * kv.re};
       });
       const cx<Real> *us = stages + ((int64_t)nn * 4 + s) * a.total + d.offset;
-      fft_fwdpath<N, E, V, +1, PS, true>(z, X, tw, w, lane);
+      fft_fwdpath<N, E, V, TP, +1, PS, true>(z, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         fa[m] = us[WP::mode(w, lane, m)];
       });
-      fft_fwdpath<N, E, V, +1, PS, true>(fa, X, tw, w, lane);
+      fft_fwdpath<N, E, V, TP, +1, PS, true>(fa, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const cx<Real> av = fa[m], zv = z[m];
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
         z[m] = {p2 * zv.re + a2.re * zv.re + a2.im * zv.im,
                 p2 * zv.im + a2.im * zv.re - a2.re * zv.im};
       });
-      fft_backpath<N, E, V, -1, PS>(z, X, Y, tw, w, lane);
+      fft_backpath<N, E, V, TP, -1, PS>(z, X, Y, tw, w, lane);
       const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
@@ -258,44 +259,59 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS>::THREADS)) rk4_w
   }
 }
 
-template <typename Real, int N, int E, int V, int PS>
+template <typename Real, int N, int E, int V, int PS, int TP>
 hipError_t launch_wave_fwd(const RunArgs &a, hipStream_t st) {
-  using SH = WaveShape<Real, N, E, V, PS>;
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
   const int grid = (a.count + SH::IPB - 1) / SH::IPB;
-  hipLaunchKernelGGL((rk4_wave<Real, N, E, V, PS>), dim3(grid), dim3(SH::THREADS), 0, st, a);
+  hipLaunchKernelGGL((rk4_wave<Real, N, E, V, PS, TP>), dim3(grid), dim3(SH::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
-template <typename Real, int N, int E, int V, int PS>
+template <typename Real, int N, int E, int V, int PS, int TP>
 hipError_t launch_wave_adj(const AdjArgs &a, hipStream_t st) {
-  using SH = WaveShape<Real, N, E, V, PS>;
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
   const int grid = (a.count + SH::IPB - 1) / SH::IPB;
-  hipLaunchKernelGGL((rk4_wave_reverse<Real, N, E, V, PS>), dim3(grid), dim3(SH::THREADS), 0, st,
-                     a);
+  hipLaunchKernelGGL((rk4_wave_reverse<Real, N, E, V, PS, TP>), dim3(grid), dim3(SH::THREADS), 0,
+                     st, a);
   return hipGetLastError();
 }
 
-template <typename Real, int N, int E, int V, int PS> constexpr Variant wave_variant() {
-  using SH = WaveShape<Real, N, E, V, PS>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, 1, SH::IPB,
-                 SH::THREADS, SH::LDS_BYTES, &launch_wave_fwd<Real, N, E, V, PS>,
-                 &launch_wave_adj<Real, N, E, V, PS>};
+template <typename Real, int N, int E, int V, int PS, int TP = 0> constexpr Variant wave_variant() {
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, TP, 1, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES, &launch_wave_fwd<Real, N, E, V, PS, TP>,
+                 &launch_wave_adj<Real, N, E, V, PS, TP>};
 }
 
-// (N, E, V, PS): N modes, E per thread, V sub-transforms per wave, one LDS
-// padding element every 2^PS.
+// (N, E, V, PS, TP): N modes, E per thread, V sub-transforms per wave, one
+// LDS padding element every 2^PS, sub-transform kind TP (0 Stockham through
+// LDS; 1 radix-8 passes with the high lane bits exchanged in registers and
+// the low ones through LDS; 2 all in registers).  The first entry of a size
+// is its default.
 static const Variant kWaveVariants[] = {
-    wave_variant<double, 128, 2, 1, 1>(),  wave_variant<double, 256, 4, 1, 2>(),
-    wave_variant<double, 256, 2, 1, 1>(),  wave_variant<double, 512, 8, 1, 3>(),
-    wave_variant<double, 512, 4, 1, 2>(),  wave_variant<double, 512, 8, 2, 2>(),
-    wave_variant<double, 1024, 16, 1, 4>(), wave_variant<double, 1024, 8, 1, 3>(),
-    wave_variant<double, 1024, 4, 1, 2>(), wave_variant<double, 1024, 8, 2, 2>(),
-    wave_variant<double, 2048, 8, 1, 3>(), wave_variant<double, 2048, 8, 1, 4>(),
-    wave_variant<double, 2048, 8, 2, 2>(), wave_variant<double, 2048, 8, 2, 3>(),
-    wave_variant<double, 2048, 16, 1, 4>(), wave_variant<double, 4096, 8, 1, 3>(),
-    wave_variant<double, 4096, 16, 2, 3>(), wave_variant<double, 4096, 16, 1, 4>(),
+    wave_variant<double, 128, 2, 1, 1>(),     wave_variant<double, 256, 4, 1, 2>(),
+    wave_variant<double, 256, 2, 1, 1>(),     wave_variant<double, 512, 8, 1, 3, 1>(),
+    wave_variant<double, 512, 8, 1, 3, 2>(),  wave_variant<double, 512, 8, 1, 3>(),
+    wave_variant<double, 512, 4, 1, 2>(),     wave_variant<double, 1024, 8, 1, 3, 1>(),
+    wave_variant<double, 1024, 8, 1, 3, 2>(), wave_variant<double, 1024, 8, 1, 3>(),
+    wave_variant<double, 1024, 4, 1, 2>(),    wave_variant<double, 1024, 16, 2, 3, 1>(),
+    wave_variant<double, 2048, 8, 1, 3, 1>(), wave_variant<double, 2048, 8, 1, 3, 2>(),
+    wave_variant<double, 2048, 8, 1, 3>(),    wave_variant<double, 2048, 8, 2, 3>(),
+    wave_variant<double, 4096, 16, 2, 3, 1>(), wave_variant<double, 4096, 8, 1, 3, 1>(),
+    wave_variant<double, 4096, 8, 1, 3>(),    wave_variant<double, 8192, 16, 2, 3, 1>(),
     wave_variant<double, 8192, 16, 2, 3>(),
 };
+
+// Reverse kernels shared with the dual-chain forward kernels (cme_dual.hip).
+template hipError_t launch_wave_adj<double, 512, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 512, 8, 1, 3, 1>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 1024, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 1024, 8, 1, 3, 1>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 2048, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 2048, 8, 1, 3, 1>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 2048, 8, 1, 3, 2>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 4096, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
+template hipError_t launch_wave_adj<double, 4096, 8, 1, 3, 1>(const AdjArgs &, hipStream_t);
 
 const Variant *variants_wave(int *count) {
   *count = (int)(sizeof(kWaveVariants) / sizeof(kWaveVariants[0]));
