@@ -32,6 +32,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_team(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_lean(&n);
+    v.insert(v.end(), a, a + n);
     return v;
   }();
   *count = (int)all.size();

@@ -75,7 +75,8 @@ struct Variant {
   int ps;          // LDS padding: one element every 2^ps (0: none)
   int tp;          // wave kernels: sub-transform kind (0 Stockham, 1 registers + LDS, 2 registers)
   int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel,
-                   // 2: two-level kernel with two transform chains (cme_dual.hip)
+                   // 2: two-level kernel with two transform chains (cme_dual.hip),
+                   // 3: two-level kernel sized for two waves per SIMD (cme_lean.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -86,6 +87,7 @@ struct Variant {
 const Variant *variants_team(int *count);  // cme_kernels.hip
 const Variant *variants_wave(int *count);  // cme_wave.hip
 const Variant *variants_dual(int *count);  // cme_dual.hip
+const Variant *variants_lean(int *count);  // cme_lean.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 }  // namespace cme
