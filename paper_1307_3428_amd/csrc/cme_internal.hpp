@@ -74,19 +74,19 @@ struct Variant {
   int v;           // wave-local sub-transforms per wave (1 for team kernels)
   int ps;          // LDS padding: one element every 2^ps (0: none)
   int tp;          // wave kernels: sub-transform kind (0 Stockham, 1 registers + LDS, 2 registers)
-  int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel,
-                   // 2: two-level kernel with two transform chains (cme_dual.hip),
-                   // 3: two-level kernel sized for two waves per SIMD (cme_lean.hip)
+  int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel
+                   // (cme_wave.hpp), 3: two-level kernel sized for two waves per
+                   // SIMD (cme_lean.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
   FwdLaunch fwd;
-  AdjLaunch adj;   // null if no adjoint kernel for this variant
+  AdjLaunch adj;   // null if no adjoint kernel for this variant (FP32)
 };
 
 const Variant *variants_team(int *count);  // cme_kernels.hip
-const Variant *variants_wave(int *count);  // cme_wave.hip
-const Variant *variants_dual(int *count);  // cme_dual.hip
+const Variant *variants_wave(int *count);      // cme_wave.hip (FP64)
+const Variant *variants_wave_f32(int *count);  // cme_wave_f32.hip
 const Variant *variants_lean(int *count);  // cme_lean.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 

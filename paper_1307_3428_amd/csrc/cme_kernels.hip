@@ -289,11 +289,19 @@ hipError_t launch_adj(const AdjArgs &a, hipStream_t st) {
           KernelShape<double, N, E, CME_PS(E)>::LDS_BYTES, &launch_fwd<double, N, E, CME_PS(E)>, \
           &launch_adj<double, N, E, CME_PS(E)>}
 
+// FP32 team kernels (forward only: the reverse path is FP64).
+#define CME_V32(N, E)                                                                      \
+  Variant{1, N, E, 1, CME_PS(E), 0, 0, KernelShape<float, N, E, CME_PS(E)>::IPB,              \
+          KernelShape<float, N, E, CME_PS(E)>::THREADS,                                    \
+          KernelShape<float, N, E, CME_PS(E)>::LDS_BYTES, &launch_fwd<float, N, E, CME_PS(E)>, \
+          nullptr}
+
 // Team kernels cover the sizes where one instance is smaller than a
 // wavefront's worth of threads (several instances share a wavefront).
 static const Variant kVariants[] = {
     CME_V64(16, 4),  CME_V64(32, 4),  CME_V64(64, 4),  CME_V64(64, 8),
-    CME_V64(128, 4), CME_V64(128, 8), CME_V64(256, 8),
+    CME_V64(128, 4), CME_V64(128, 8), CME_V64(256, 8), CME_V32(16, 4),
+    CME_V32(32, 4),  CME_V32(64, 4),  CME_V32(128, 4), CME_V32(256, 8),
 };
 
 const Variant *variants_team(int *count) {

@@ -205,3 +205,99 @@ def test_adjoint_matches_oracle(cme, orc):
     assert rel_err(g["g_kappa"].cpu().numpy(), ref["g_kappa"]) <= 1e-11
     gain = g["g_ain"].cpu().numpy().reshape(-1, 2)
     assert rel_err(gain[:, 0] + 1j * gain[:, 1], ref["g_ain"]) <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# FP32 path: FP32 transforms and state, FP64 time / detuning bookkeeping.
+# Bar: relative L2 error <= 1e-4 against the FP64 oracle.
+# ---------------------------------------------------------------------------
+FP32_TOL = 1e-4
+
+
+def _variant_params_f32():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
+                for k in C.cme_list_kernels(C.CME_F32, n)]
+    except Exception:
+        return [(16, 0)]
+
+
+def gpu_run32(C, packed, h, steps, step0=0, kid=None, n=None):
+    import torch
+    with C.Plan(packed, h, precision=C.CME_F32) as plan:
+        if kid is not None:
+            plan.select(n, kid)
+        A = plan.state(packed.a0)
+        assert A.dtype == torch.complex64
+        plan.run(A, steps, step0=step0)
+        torch.cuda.synchronize()
+        return A.cpu().numpy().astype(np.complex128), plan.status()
+
+
+@pytest.mark.parametrize("n,kid", _variant_params_f32())
+def test_each_fp32_variant_matches_oracle(cme, orc, n, kid):
+    info = cme.cme_kernel_info(kid)
+    assert info["precision"] == cme.CME_F32
+    print(f"variant {info['name']}", flush=True)
+    batch = 5 if info["instances_per_group"] > 1 else 2
+    p = W.pack(moderate_batch(3000 + n + kid, [n] * batch))
+    y, st = gpu_run32(cme, p, 0.01, 4, step0=5, kid=kid, n=n)
+    ref, _ = orc.run(p, 0.01, 4, step0=5)
+    errs = per_instance_err(p, y, ref)
+    assert max(errs) <= 2e-6, errs
+    assert not st.any()
+
+
+def rk4_stable(inst, h):
+    """|R(h lambda_mu)| <= 1 for every mode at both ends of the detuning ramp
+    (R the classic RK4 stability polynomial); the library refuses other
+    instances with CME_EUNSTABLE."""
+    out = True
+    for sg in (inst.sigma0, inst.sigma1):
+        z = h * (-0.5 * inst.kappa + 1j * (inst.omega - sg))
+        r = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+        out &= bool(np.all(np.abs(r) <= 1 + 1e-12))
+    return out
+
+
+def test_fp32_uneven_octave_subset(cme, orc):
+    """Instances of the uneven-octave batch (N in {1024, ..., 8192}, h = 2e-4),
+    all sizes in one FP32 plan; each size class against the FP64 oracle over
+    a horizon the oracle finishes in seconds."""
+    wl = W.uneven_octave(batch=64, n_steps=1)
+    by_n = {}
+    for i, inst in enumerate(wl.instances):
+        if rk4_stable(inst, wl.h):
+            by_n.setdefault(inst.n_modes, []).append(i)
+    horizon = {1024: 1000, 2048: 400, 4096: 100, 8192: 20}
+    for n, steps in sorted(horizon.items()):
+        pick = [wl.instances[i] for i in by_n[n][:2]]
+        p = W.pack(pick)
+        y, st = gpu_run32(cme, p, wl.h, steps)
+        ref, _ = orc.run(p, wl.h, steps)
+        errs = per_instance_err(p, y, ref)
+        print(f"N={n} steps={steps} fp32 rel err {max(errs):.2e}", flush=True)
+        assert max(errs) <= FP32_TOL, (n, errs)
+        assert not st.any()
+
+
+def test_fp32_full_horizon_against_fp64_path(cme):
+    """Full 2e4-step horizon of two uneven-octave instances per size up to
+    N = 4096: FP32 against the FP64 GPU path (which is held to the oracle at
+    1e-10 by the tests above); labelled as such, not an oracle comparison."""
+    import torch
+    wl = W.uneven_octave(batch=64, n_steps=20000)
+    seen = {}
+    pick = []
+    for inst in wl.instances:
+        if inst.n_modes <= 4096 and seen.get(inst.n_modes, 0) < 2:
+            seen[inst.n_modes] = seen.get(inst.n_modes, 0) + 1
+            pick.append(inst)
+    p = W.pack(pick)
+    y32, st = gpu_run32(cme, p, wl.h, wl.n_steps)
+    y64, st64 = gpu_run(cme, p, wl.h, wl.n_steps)
+    errs = per_instance_err(p, y32, y64)
+    print("fp32 vs fp64 after 2e4 steps:", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) <= FP32_TOL, errs
+    assert not st.any() and not st64.any()
