@@ -276,6 +276,11 @@ class Plan:
     def status(self) -> np.ndarray:
         return cme_status(self.handle, self.batch)
 
+    def set_stream(self, stream=None):
+        """Enqueue later calls on `stream` (a torch.cuda.Stream, a raw handle,
+        or None for the null stream)."""
+        cme_set_stream(self.handle, stream)
+
     def kernel(self, n_modes: int) -> dict:
         """Shape of the kernel variant the plan uses for this size."""
         return cme_kernel_info(cme_plan_kernel(self.handle, n_modes))

@@ -49,6 +49,10 @@ struct SizeClass {
   std::vector<int32_t> ids;
   int32_t *d_order = nullptr;
   void *d_tw = nullptr;
+  // classes after the first run on their own plan-owned stream, forked from
+  // and joined back into the caller's stream with events
+  hipStream_t side = nullptr;
+  hipEvent_t done = nullptr;
 };
 
 }  // namespace
@@ -68,6 +72,7 @@ struct cme_plan {
   double *d_omega = nullptr;
   int32_t *d_flags = nullptr;
   std::vector<SizeClass> classes;
+  hipEvent_t fork = nullptr;  // recorded on the caller's stream before the side launches
   // adjoint scratch (grown on demand)
   void *d_stages = nullptr;
   size_t stages_bytes = 0;
@@ -178,7 +183,10 @@ void free_plan(cme_plan *p) {
   for (auto &c : p->classes) {
     if (c.d_order) (void)hipFree(c.d_order);
     if (c.d_tw) (void)hipFree(c.d_tw);
+    if (c.done) (void)hipEventDestroy(c.done);
+    if (c.side) (void)hipStreamDestroy(c.side);
   }
+  if (p->fork) (void)hipEventDestroy(p->fork);
   void *bufs[] = {p->d_inst, p->d_kappa, p->d_omega, p->d_flags, p->d_stages,
                   p->d_ckpt, p->d_state, p->d_gA};
   for (void *b : bufs)
@@ -208,11 +216,24 @@ cme::RunArgs run_args(const cme_plan *p, const SizeClass &c, void *A, int64_t st
   return a;
 }
 
+// One launch per size class.  The classes touch disjoint instances, so all
+// but the first run on side streams that wait for everything enqueued before
+// on the caller's stream and are joined back into it: the classes share the
+// chip, and the call stays ordered on the caller's stream (and capturable
+// into a graph, where it becomes parallel branches).
 int launch_forward(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
                    void *ckpt, void *stages) {
-  for (auto &c : p->classes) {
+  const size_t nc = p->classes.size();
+  if (nc > 1) HIP_TRY(hipEventRecord(p->fork, p->stream));
+  for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
+  for (size_t i = 0; i < nc; ++i) {
+    SizeClass &c = p->classes[i];
     const cme::RunArgs a = run_args(p, c, A, step0, n_steps, ckpt_every, ckpt, stages);
-    if (c.var->fwd(a, p->stream) != hipSuccess) return CME_EHIP;
+    if (c.var->fwd(a, i == 0 ? p->stream : c.side) != hipSuccess) return CME_EHIP;
+  }
+  for (size_t i = 1; i < nc; ++i) {
+    HIP_TRY(hipEventRecord(p->classes[i].done, p->classes[i].side));
+    HIP_TRY(hipStreamWaitEvent(p->stream, p->classes[i].done, 0));
   }
   return CME_OK;
 }
@@ -403,8 +424,15 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
                   hipMemcpyHostToDevice) != hipSuccess)
       rc = CME_EHIP;
     if (rc == CME_OK) rc = upload_twiddles(c.n, precision, &c.d_tw);
+    if (rc == CME_OK && !p->classes.empty() &&
+        (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess))
+      rc = CME_EHIP;
     p->classes.push_back(c);
   }
+  if (rc == CME_OK && p->classes.size() > 1 &&
+      hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) != hipSuccess)
+    rc = CME_EHIP;
   if (rc == CME_OK && (flags & CME_INIT_AUTOTUNE)) rc = autotune(p);
   if (rc != CME_OK) {
     free_plan(p);

@@ -301,3 +301,53 @@ def test_fp32_full_horizon_against_fp64_path(cme):
     print("fp32 vs fp64 after 2e4 steps:", ["%.1e" % e for e in errs], flush=True)
     assert max(errs) <= FP32_TOL, errs
     assert not st.any() and not st64.any()
+
+
+# ---------------------------------------------------------------------------
+# Uneven batches: size classes run concurrently; the whole call captures into
+# a graph whose replays equal the eager calls bit for bit.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("sizes", [[2048, 1024, 512, 128, 2048, 4096, 16], [2048] * 4])
+def test_graph_capture_replays_match_eager(cme, sizes):
+    import torch
+    p = W.pack(moderate_batch(9, sizes))
+    with cme.Plan(p, 0.005) as plan:
+        A = plan.state(p.a0)
+        B = A.clone()
+        s = torch.cuda.Stream()
+        plan.set_stream(s)
+        with torch.cuda.stream(s):
+            warm = A.clone()
+            plan.run(warm, 2)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.run(A, 10)
+        plan.set_stream(None)
+        for _ in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            plan.run(B, 10)
+            torch.cuda.synchronize()
+            assert torch.equal(A, B)
+        assert not plan.status().any()
+
+
+def test_concurrent_classes_match_separate_plans(cme):
+    """A plan over several size classes (launched concurrently) gives, for
+    each instance, exactly the result of a plan holding only its class."""
+    import torch
+    sizes = [4096, 1024, 2048, 1024, 512, 4096]
+    insts = moderate_batch(10, sizes)
+    p = W.pack(insts)
+    with cme.Plan(p, 0.005) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 20)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+    for n in sorted(set(sizes)):
+        idx = [i for i, x in enumerate(sizes) if x == n]
+        q = W.pack([insts[i] for i in idx])
+        yq, _ = gpu_run(cme, q, 0.005, 20)
+        for j, i in enumerate(idx):
+            assert np.array_equal(y[p.slice(i)], yq[q.slice(j)]), (n, i)
