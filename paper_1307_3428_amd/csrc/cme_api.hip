@@ -475,7 +475,7 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
   const int64_t K = ckpt_every > 0 ? std::min<int64_t>(ckpt_every, n_steps) : n_steps;
   if (K > (1 << 20)) return CME_EINVAL;
   const int64_t nseg = (n_steps + K - 1) / K;
-  int rc = grow(&p->d_stages, &p->stages_bytes, vec * 4 * (size_t)K);
+  int rc = grow(&p->d_stages, &p->stages_bytes, vec * 8 * (size_t)K);
   if (rc != CME_OK) return rc;
   rc = grow(&p->d_state, &p->state_bytes, vec);
   if (rc != CME_OK) return rc;

@@ -514,6 +514,10 @@ template <int N, int E, int V, int TP = 0> struct WavePlan {
   __device__ static int mode(int w, int l, int m) {
     return l + 64 * (w * Q + m % Q) + N1 * (m / Q);
   }
+  // storage position of the element a thread holds in slot m on the
+  // transformed (scrambled) side: a bijection onto [0, N) with lanes
+  // contiguous, used to save and reload time-domain fields
+  __device__ static int tslot(int w, int l, int m) { return l + 64 * (w + W * m); }
 };
 
 template <int N, int E, int V, int TP, typename Real> struct WaveTwiddles {

@@ -34,7 +34,8 @@ struct RunArgs {
   void *ckpt;              // complex Real [n_steps / ckpt_every][total] or null
   int64_t total;
   int32_t *flags;          // [batch] non-finite flags
-  void *stages;            // adjoint recompute: stage inputs [K][4][total] or null
+  void *stages;            // adjoint recompute: per step and stage, the stage input u_s
+                           // and its inverse transform a_s, [K][4][2][total], or null
 };
 
 // Arguments of one reverse (adjoint) launch over one segment of one class.
@@ -43,7 +44,7 @@ struct AdjArgs {
   const int32_t *order;
   int32_t count;
   int32_t n_seg;           // steps in this segment
-  const void *stages;      // stage inputs u_s of every step of the segment [K][4][total]
+  const void *stages;      // u_s and a_s of every step of the segment [K][4][2][total]
   void *gA;                // in: cotangent of the state after the segment; out: before
   const double *kappa;
   const double *omega;
@@ -55,6 +56,14 @@ struct AdjArgs {
   double *g_kappa;         // [total] or null (accumulated)
   double *g_ain;           // [2 batch] or null (accumulated)
 };
+
+// Offset of the stage-s record of step n in the adjoint stage buffer: the
+// stage input u_s (mode order, packed like A) at this offset, the inverse
+// transform a_s = IDFT(u_s) (in the kernel's time-domain slot order) total
+// elements further.
+__host__ __device__ inline int64_t stage_offset(int64_t n, int s, int64_t total) {
+  return (n * 4 + s) * 2 * total;
+}
 
 __host__ __device__ inline double sigma_at(double sigma0, double sigma1, double tau_ramp,
                                            double t) {

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__((KernelShape<Real, N, E, PS>::THREADS))
         else v[m] = {y[m].re + ch * k[m].re, y[m].im + ch * k[m].im};
       });
       if (stages != nullptr && active) {
-        cx<Real> *st = stages + ((int64_t)n * 4 + s) * a.total + d.offset;
+        cx<Real> *st = stages + stage_offset(n, s, a.total) + d.offset;
         sfor<0, E>([&](auto mi) { st[t + decltype(mi)::value * T] = v[decltype(mi)::value]; });
       }
       fft_team<N, E, +1, PS, PING, 0>(v, buf0, buf1, tw, t);
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__((KernelShape<Real, N, E, PS>::THREADS))
         // z <- (-i g0/N) kbar, then inverse transform
         z[m] = {gn * kv.im, -gn * kv.re};
       });
-      const cx<Real> *us = stages + ((int64_t)nn * 4 + s) * a.total + d.offset;
+      const cx<Real> *us = stages + stage_offset(nn, s, a.total) + d.offset;
       fft_team<N, E, +1, PS, PING, 0>(z, buf0, buf1, tw, t);
       sfor<0, E>([&](auto mi) { fa[decltype(mi)::value] = us[t + decltype(mi)::value * T]; });
       fft_team<N, E, +1, PS, PING, (X & 1)>(fa, buf0, buf1, tw, t);

@@ -329,7 +329,7 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
         sfor<0, E>([&](auto mi) { u[decltype(mi)::value] = y[decltype(mi)::value]; });
       }
       if (stages != nullptr) {
-        cx<Real> *st = stages + ((int64_t)n * 4 + s) * a.total + d.offset;
+        cx<Real> *st = stages + stage_offset(n, s, a.total) + d.offset;
         sfor<0, E>([&](auto mi) {
           constexpr int m = decltype(mi)::value;
           st[WP::mode(w, lane, m)] = u[m];
@@ -337,6 +337,13 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
       }
       sfor<0, E>([&](auto mi) { v[decltype(mi)::value] = u[decltype(mi)::value]; });
       lean_fwdpath<N, E, +1, PS, !SH::TWO>(v, X, tw, w, lane);
+      if (stages != nullptr) {
+        cx<Real> *st = stages + stage_offset(n, s, a.total) + a.total + d.offset;
+        sfor<0, E>([&](auto mi) {
+          constexpr int m = decltype(mi)::value;
+          st[WP::tslot(w, lane, m)] = v[m];
+        });
+      }
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
@@ -381,6 +388,136 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
+// Reverse sweep over one checkpoint segment (the discrete adjoint of the
+// RK4 map of rk4_lean, steps in reverse).  Per stage, from the cotangent
+// ybar' of the step's output and ubar_{s+1} of the later stage:
+//   kbar_s = w_s h ybar' + c_{s+1} h ubar_{s+1}
+//   ubar_s = conj(L_s) kbar_s + V(-i g0 kbar_s),
+//   V(w') = DFT[2 |a_s|^2 z + a_s^2 conj(z)],  z = IDFT(w') / N,
+// with a_s = IDFT(u_s) read back from the stage buffer (stored by the
+// forward recompute), so a stage costs two transforms; ybar = ybar' +
+// sum_s ubar_s, and the parameter gradients accumulate
+//   gbar_omega += Re(conj(kbar) i u),  gbar_kappa -= Re(conj(kbar) u) / 2,
+//   gbar_Ain   += sqrt(kappa_ext) kbar at mu = 0.
+// The 1/N of z is folded into g0/N.
+template <typename Real, int N, int E, int PS>
+__global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS)) rk4_lean_reverse(AdjArgs a) {
+  using SH = LeanShape<Real, N, E, PS>;
+  using WP = WavePlan<N, E, 1, 0>;
+  constexpr int W = WP::W;
+  __shared__ cx<Real> lds[SH::IPB * SH::PER_INST];
+
+  const int lane = (int)threadIdx.x & 63;
+  const int wv = (int)threadIdx.x >> 6;
+  const int sub = W == 1 ? wv : 0;
+  const int w = W == 1 ? 0 : wv;
+  const int slot = (int)blockIdx.x * SH::IPB + sub;
+  if constexpr (W == 1) {
+    if (slot >= a.count) return;  // waves of a W = 1 group never synchronise
+  }
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  cx<Real> *X = lds + sub * SH::PER_INST;
+  cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;
+  const double *kap = a.kappa + d.offset;
+  const double *omg = a.omega + d.offset;
+  cx<Real> *gA = reinterpret_cast<cx<Real> *>(a.gA) + d.offset;
+  const cx<Real> *stages = reinterpret_cast<const cx<Real> *>(a.stages);
+
+  LeanTw<N, E, Real> tw;
+  load_lean_twiddles<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+
+  cx<Real> yb1[E], yb[E], ub[E], z[E];
+  Real lr[E], gom[E], gka[E];
+  double om[E];
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int i = WP::mode(w, lane, m);
+    yb1[m] = gA[i];
+    lr[m] = (Real)(-0.5 * kap[i]);
+    om[m] = omg[i];
+    gom[m] = (Real)0;
+    gka[m] = (Real)0;
+    ub[m] = {(Real)0, (Real)0};
+  });
+  const bool pump_owner = (w == 0 && lane == 0);
+  cx<Real> gain = {(Real)0, (Real)0};
+  const Real gn = (Real)d.g0n;
+  const double h = a.h;
+
+  for (int nn = a.n_seg - 1; nn >= 0; --nn) {
+    const double t0 = (double)(a.step_first + nn) * h;
+    sfor<0, E>([&](auto mi) { yb[decltype(mi)::value] = yb1[decltype(mi)::value]; });
+    sfor<0, 4>([&](auto ri) {
+      constexpr int s = 3 - decltype(ri)::value;
+      const Real wb = (Real)(kLeanW[s] / 6.0 * h);
+      const Real cn = (Real)(s < 3 ? kLeanC[s < 3 ? s + 1 : 3] * h : 0.0);
+      // the stage record is loaded first, so that its latency hides behind
+      // the transforms
+      const cx<Real> *rec = stages + stage_offset(nn, s, a.total) + d.offset;
+      cx<Real> ar[E], ur[E];
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        ar[m] = rec[a.total + WP::tslot(w, lane, m)];
+        ur[m] = rec[WP::mode(w, lane, m)];
+      });
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        cx<Real> kv = {wb * yb1[m].re, wb * yb1[m].im};
+        if constexpr (s < 3) kv = {kv.re + cn * ub[m].re, kv.im + cn * ub[m].im};
+        z[m] = {gn * kv.im, -gn * kv.re};
+      });
+      lean_fwdpath<N, E, +1, PS, !SH::TWO>(z, X, tw, w, lane);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        const cx<Real> av = ar[m], zv = z[m];
+        const Real p2 = (Real)2 * (av.re * av.re + av.im * av.im);
+        const cx<Real> a2 = {av.re * av.re - av.im * av.im, (Real)2 * av.re * av.im};
+        z[m] = {p2 * zv.re + a2.re * zv.re + a2.im * zv.im,
+                p2 * zv.im + a2.im * zv.re - a2.re * zv.im};
+      });
+      lean_backpath<N, E, -1, PS>(z, X, Y, tw, w, lane);
+      const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kLeanC[s] * h);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        cx<Real> kv = {wb * yb1[m].re, wb * yb1[m].im};
+        if constexpr (s < 3) kv = {kv.re + cn * ub[m].re, kv.im + cn * ub[m].im};
+        const cx<Real> u = ur[m];
+        const Real det = (Real)(om[m] - sig);
+        const cx<Real> unew = {lr[m] * kv.re + det * kv.im + z[m].re,
+                               lr[m] * kv.im - det * kv.re + z[m].im};
+        ub[m] = unew;
+        yb[m] = cadd(yb[m], unew);
+        gom[m] += kv.im * u.re - kv.re * u.im;
+        gka[m] -= (Real)0.5 * (kv.re * u.re + kv.im * u.im);
+        if constexpr (m == E / 2) {
+          if (pump_owner) gain = cadd(gain, kv);
+        }
+      });
+    });
+    sfor<0, E>([&](auto mi) { yb1[decltype(mi)::value] = yb[decltype(mi)::value]; });
+  }
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int i = WP::mode(w, lane, m);
+    gA[i] = yb1[m];
+    if (a.g_omega) a.g_omega[d.offset + i] += (double)gom[m];
+    if (a.g_kappa) a.g_kappa[d.offset + i] += (double)gka[m];
+  });
+  if (pump_owner && a.g_ain) {
+    a.g_ain[2 * id] += d.sqrt_kext * (double)gain.re;
+    a.g_ain[2 * id + 1] += d.sqrt_kext * (double)gain.im;
+  }
+}
+
+template <typename Real, int N, int E, int PS>
+hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st) {
+  using SH = LeanShape<Real, N, E, PS>;
+  const int grid = (a.count + SH::IPB - 1) / SH::IPB;
+  hipLaunchKernelGGL((rk4_lean_reverse<Real, N, E, PS>), dim3(grid), dim3(SH::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename Real, int N, int E, int PS>
 hipError_t launch_lean_fwd(const RunArgs &a, hipStream_t st) {
   using SH = LeanShape<Real, N, E, PS>;
@@ -389,17 +526,19 @@ hipError_t launch_lean_fwd(const RunArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// defined in cme_wave.hip: the reverse kernel does not depend on how the
-// forward trajectory was evaluated
-template <typename Real, int N, int E, int V, int PS, int TP>
-hipError_t launch_wave_adj(const AdjArgs &a, hipStream_t st);
-
 template <typename Real, int N, int E, int PS> constexpr Variant lean_variant() {
   using SH = LeanShape<Real, N, E, PS>;
   return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, 0, 3, SH::IPB,
                  SH::THREADS, SH::LDS_BYTES, &launch_lean_fwd<Real, N, E, PS>,
-                 &launch_wave_adj<Real, N, E, 1, PS, 0>};
+                 &launch_lean_adj<Real, N, E, PS>};
 }
+
+// The wave kernels with E = 8, V = 1 and Stockham sub-transforms store their
+// stage records in the same slot order and use this reverse sweep too.
+template hipError_t launch_lean_adj<double, 512, 8, 3>(const AdjArgs &, hipStream_t);
+template hipError_t launch_lean_adj<double, 1024, 8, 3>(const AdjArgs &, hipStream_t);
+template hipError_t launch_lean_adj<double, 2048, 8, 3>(const AdjArgs &, hipStream_t);
+template hipError_t launch_lean_adj<double, 4096, 8, 3>(const AdjArgs &, hipStream_t);
 
 static const Variant kLeanVariants[] = {
     lean_variant<double, 512, 8, 3>(),

@@ -16,12 +16,6 @@ static const Variant kWaveVariants[] = {
     wave_variant<double, 8192, 16, 2, 3, 1>(), wave_variant<double, 8192, 16, 2, 3>(),
 };
 
-// Reverse kernels also used by the lean forward kernels (cme_lean.hip).
-template hipError_t launch_wave_adj<double, 512, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
-template hipError_t launch_wave_adj<double, 1024, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
-template hipError_t launch_wave_adj<double, 2048, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
-template hipError_t launch_wave_adj<double, 4096, 8, 1, 3, 0>(const AdjArgs &, hipStream_t);
-
 const Variant *variants_wave(int *count) {
   *count = (int)(sizeof(kWaveVariants) / sizeof(kWaveVariants[0]));
   return kWaveVariants;

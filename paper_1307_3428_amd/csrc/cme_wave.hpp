@@ -98,13 +98,22 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
         else v[m] = {y[m].re + ch * k[m].re, y[m].im + ch * k[m].im};
       });
       if (stages != nullptr) {
-        cx<Real> *st = stages + ((int64_t)n * 4 + s) * a.total + d.offset;
+        cx<Real> *st = stages + stage_offset(n, s, a.total) + d.offset;
         sfor<0, E>([&](auto mi) {
           constexpr int m = decltype(mi)::value;
           st[WP::mode(w, lane, m)] = v[m];
         });
       }
       fft_fwdpath<N, E, V, TP, +1, PS, !SH::TWO>(v, X, tw, w, lane);
+      if constexpr (V == 1 && TP == 0) {
+        if (stages != nullptr) {
+          cx<Real> *st = stages + stage_offset(n, s, a.total) + a.total + d.offset;
+          sfor<0, E>([&](auto mi) {
+            constexpr int m = decltype(mi)::value;
+            st[WP::tslot(w, lane, m)] = v[m];
+          });
+        }
+      }
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
@@ -213,7 +222,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
         if constexpr (s < 3) kv = {kv.re + cn * ub[m].re, kv.im + cn * ub[m].im};
         z[m] = {gn * kv.im, -gn * kv.re};
       });
-      const cx<Real> *us = stages + ((int64_t)nn * 4 + s) * a.total + d.offset;
+      const cx<Real> *us = stages + stage_offset(nn, s, a.total) + d.offset;
       fft_fwdpath<N, E, V, TP, +1, PS, true>(z, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
@@ -279,10 +288,20 @@ hipError_t launch_wave_adj(const AdjArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// The reverse (adjoint) kernels exist in FP64 only.
+// defined in cme_lean.hip (FP64, E = 8, PS = 3): the reverse sweep that
+// reads the stored time-domain stage fields (two transforms per stage)
+template <typename Real, int N, int E, int PS>
+hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
+
+// The reverse (adjoint) kernels exist in FP64 only.  Variants that store the
+// time-domain stage fields in the lean slot order (E = 8, V = 1, Stockham
+// sub-transforms, 1-in-8 padding) share the lean reverse sweep; the others
+// recompute the field from the stage input.
 template <typename Real, int N, int E, int V, int PS, int TP> constexpr AdjLaunch wave_adj_ptr() {
-  if constexpr (std::is_same<Real, double>::value) return &launch_wave_adj<Real, N, E, V, PS, TP>;
-  else return nullptr;
+  if constexpr (!std::is_same<Real, double>::value) return nullptr;
+  else if constexpr (E == 8 && V == 1 && TP == 0 && PS == 3 && N >= 512 && N <= 4096)
+    return &launch_lean_adj<Real, N, E, PS>;
+  else return &launch_wave_adj<Real, N, E, V, PS, TP>;
 }
 
 template <typename Real, int N, int E, int V, int PS, int TP = 0> constexpr Variant wave_variant() {

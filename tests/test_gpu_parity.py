@@ -185,6 +185,30 @@ def test_nonfinite_flag_is_per_instance(cme):
         assert np.isfinite(out[p.slice(0)]).all() and np.isfinite(out[p.slice(2)]).all()
 
 
+@pytest.mark.parametrize("sizes", [[512, 2048], [1024, 4096]])
+def test_adjoint_matches_oracle_two_level(cme, orc, sizes):
+    """Reverse sweeps of the two-level kernels (stage records with the stored
+    time-domain field) against the oracle's adjoint."""
+    import torch
+    p = W.pack(moderate_batch(11 + sizes[0], sizes))
+    h, steps, K = 0.005, 9, 4
+    rng = np.random.default_rng(12)
+    target = rng.uniform(0, 0.01, p.total)
+    yT, _ = orc.run(p, h, steps)
+    gT = 4 * (np.abs(yT) ** 2 - target) * yT
+    ref = orc.adjoint(p, h, steps, gT)
+    with cme.Plan(p, h) as plan:
+        for n in sizes:
+            print(n, plan.kernel(n)["name"], flush=True)
+        g = plan.adjoint(plan.state(p.a0), plan.state(gT), steps, ckpt_every=K)
+        torch.cuda.synchronize()
+    assert rel_err(g["gA_0"].cpu().numpy(), ref["gy0"]) <= 1e-11
+    assert rel_err(g["g_omega"].cpu().numpy(), ref["g_omega"]) <= 1e-11
+    assert rel_err(g["g_kappa"].cpu().numpy(), ref["g_kappa"]) <= 1e-11
+    gain = g["g_ain"].cpu().numpy().reshape(-1, 2)
+    assert rel_err(gain[:, 0] + 1j * gain[:, 1], ref["g_ain"]) <= 1e-11
+
+
 def test_adjoint_matches_oracle(cme, orc):
     import torch
     insts = moderate_batch(8, [64, 256, 16])
