@@ -18,7 +18,11 @@ Also reported on the same JSON line:
                 sample of the same workload on this host's cores;
   adjoint       forward-with-checkpoints and adjoint times for the N = 2048,
                 5000-step gradient workload and their ratio;
-  single        a single N = 1024 instance (soliton ramp) on one workgroup.
+  single        a single N = 1024 instance (soliton ramp) on one workgroup;
+  fp32          the same sweep in FP32 (FP64 time bookkeeping);
+  uneven        the uneven-octave batch (512 instances, N in {1024, ..., 8192},
+                h = 2e-4, 2e4 steps) in FP64 and FP32, classic RK4 on the
+                instances it is stable for (the excluded count is reported).
 """
 import argparse
 import hashlib
@@ -34,7 +38,8 @@ sys.path.insert(0, ROOT)
 METRIC = "mode-steps/s (FP64, 1 GPU) at ≤1e-10 rel. error vs oracle; adjoint/forward ratio"
 FP64_PEAK_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "rk4_wave_sweep_n2048_counters.txt")
-KERNEL_SOURCES = ("cme_fft.hpp", "cme_kernels.hip", "cme_wave.hip", "cme_internal.hpp")
+KERNEL_SOURCES = ("cme_fft.hpp", "cme_internal.hpp", "cme_wave.hpp", "cme_wave.hip", "cme_lean.hip",
+                  "cme_kernels.hip")
 
 
 def kernel_source_hash() -> str:
@@ -223,6 +228,8 @@ def main() -> int:
     if not args.no_extras:
         out["adjoint"] = adjoint_leg(C, W, torch)
         out["single"] = single_leg(C, W, torch)
+        out["fp32"] = fp32_leg(C, W, torch, rk_steps)
+        out["uneven"] = uneven_leg(C, W, torch)
     print(json.dumps(out))
     return 0
 
@@ -254,6 +261,60 @@ def adjoint_leg(C, W, torch):
     return {"workload": "adjoint_n2048: N=2048, 5000 RK4 steps, checkpoints every 100",
             "forward_ms": fwd, "adjoint_ms": bwd, "adjoint_over_forward": bwd / fwd,
             "forward_plus_adjoint_over_forward": (fwd + bwd) / fwd}
+
+
+def timed_run(plan, A, steps, torch):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.run(A, steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def fp32_leg(C, W, torch, rk_steps):
+    """The 256 x N=2048 sweep in FP32 (same horizon), autotuned."""
+    wl = W.sweep_n2048(n_steps=rk_steps)
+    p = W.pack(wl.instances)
+    with C.Plan(p, wl.h, precision=C.CME_F32, flags=C.CME_INIT_AUTOTUNE) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 1000)
+        torch.cuda.synchronize()
+        s = timed_run(plan, A, rk_steps, torch)
+        k = plan.kernel(2048)
+    return {"workload": f"sweep_n2048 in FP32, {rk_steps} RK4 steps",
+            "mode_steps_per_s": p.total * rk_steps / s, "kernel": k["name"]}
+
+
+def rk4_stable(inst, h):
+    import numpy as np
+    ok = True
+    for sg in (inst.sigma0, inst.sigma1):
+        z = h * (-0.5 * inst.kappa + 1j * (inst.omega - sg))
+        ok &= bool(np.all(np.abs(1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24) <= 1 + 1e-12))
+    return ok
+
+
+def uneven_leg(C, W, torch, steps=20000):
+    """The uneven-octave batch, FP64 and FP32, one plan per precision (size
+    classes launched concurrently), on the classically RK4-stable instances."""
+    wl = W.uneven_octave(n_steps=steps)
+    keep = [x for x in wl.instances if rk4_stable(x, wl.h)]
+    p = W.pack(keep)
+    out = {"workload": f"uneven_octave: {len(keep)} of {len(wl.instances)} instances "
+                       f"(classic RK4 stable), N in {{1024,2048,4096,8192}}, {steps} steps",
+           "excluded_unstable": len(wl.instances) - len(keep),
+           "by_n": {str(n): int(sum(1 for x in keep if x.n_modes == n))
+                    for n in (1024, 2048, 4096, 8192)}}
+    for prec, name in ((C.CME_F64, "fp64"), (C.CME_F32, "fp32")):
+        with C.Plan(p, wl.h, precision=prec, flags=C.CME_INIT_AUTOTUNE) as plan:
+            A = plan.state(p.a0)
+            plan.run(A, 200)
+            torch.cuda.synchronize()
+            s = timed_run(plan, A, steps, torch)
+            out[name] = {"mode_steps_per_s": p.total * steps / s, "seconds": s,
+                         "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
+    return out
 
 
 def single_leg(C, W, torch):
