@@ -170,8 +170,10 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * precision, modes N, modes per thread E, wave-local sub-transforms per wave
  * V, LDS padding shift (one pad element every 2^shift), kind (0: one
  * transform per team of threads with workgroup barriers, 1: two-level
- * transform with one workgroup barrier per transform, 3: two-level transform
- * with twiddles rebuilt on use, sized for two wavefronts per SIMD),
+ * transform with one workgroup barrier per transform, 2: two-level
+ * transforms in four rounds of two interleaved transforms per RK4 step,
+ * 3: two-level transform with twiddles rebuilt on use, sized for two
+ * wavefronts per SIMD),
  * instances per workgroup, workgroup size, LDS bytes, sub-transform exchange
  * policy (0: all through LDS, 1: high lane bits in registers, low through
  * LDS).  Returns 10, or CME_EINVAL. */

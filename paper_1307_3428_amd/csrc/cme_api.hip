@@ -26,7 +26,9 @@ const Variant *variants(int *count) {
   static const std::vector<Variant> all = [] {
     std::vector<Variant> v;
     int n = 0;
-    const Variant *a = variants_wave(&n);
+    const Variant *a = variants_duo(&n);
+    v.insert(v.end(), a, a + n);
+    a = variants_wave(&n);
     v.insert(v.end(), a, a + n);
     a = variants_lean(&n);
     v.insert(v.end(), a, a + n);
@@ -98,9 +100,10 @@ const Variant *all_variants(int *count) { return cme::variants(count); }
 // The default kernel for a size is the first compiled variant listed for it
 // (the tables list the preferred shape first).
 // Default kernel of a size when the plan is not autotuned: the first
-// variant of that size in table order, except that the lean kernel is
-// preferred where its eight wavefronts per instance fill two per SIMD
-// (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
+// variant of that size in table order (the paired-transform kernels come
+// first; their tables list the preferred shape first), except that the lean
+// kernel is preferred where its eight wavefronts per instance fill two per
+// SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
 // per CU).
 const Variant *default_variant(int precision, int n) {
   int cnt = 0;

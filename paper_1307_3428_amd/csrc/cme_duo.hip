@@ -1,0 +1,560 @@
+// cme_duo.hip -- RK4 kernel evaluating each step as four rounds of two
+// independent transforms, interleaved inside every wavefront.
+//
+// Same RK4 map as cme_wave.hpp, in a different but mathematically identical
+// order.  With L_s = -kappa/2 + i(omega' - sigma(t_s)), p the pump at mu = 0,
+// W_s = L_s u_s + p, IDFT the unnormalised inverse transform of Eq. (4) and
+// K'_s = DFT(b_s) (so the four-wave-mixing term is (g0/N) K'_s):
+//   k_s        = W_s + i (g0/N) K'_s,           b_s = |a_s|^2 a_s,
+//   a_s        = IDFT(u_s),  IDFT(k_s) = IDFT(W_s) + i g0 b_s  (IDFT DFT = N),
+//   a_{s+1}    = IDFT(y) + c_{s+1} h (IDFT(W_s) + i g0 b_s).
+// Hence, with Y = IDFT(y) and Z_s = IDFT(W_s):
+//   R0: Y, Z_1                 (inverse transforms of y and W_1 = L_1 y + p)
+//       a_2 = Y + h/2 (Z_1 + i g0 b_1)
+//   R1: K'_1, K'_2             (forward transforms of b_1 = |Y|^2 Y and b_2)
+//       k_1, u_2, W_2, k_2, u_3, W_3
+//   R2: Z_2, Z_3               (inverse transforms of W_2 and W_3)
+//       a_3 = Y + h/2 (Z_2 + i g0 b_2),  a_4 = Y + h (Z_3 + i g0 b_3)
+//   R3: K'_3, K'_4             (forward transforms of b_3 and b_4)
+//       k_3, u_4, W_4, k_4;  y += h/6 (k_1 + 2 k_2 + 2 k_3 + k_4).
+// Eight transforms in four rounds; the two of a round have the same
+// direction and structure, so their passes are interleaved: while one
+// transform's LDS exchange is in flight the wave computes the other's
+// butterflies.  One workgroup barrier per round (two buffer sets, used by
+// alternate rounds).  The transform is that of cme_lean.hpp.
+#include <type_traits>
+
+#include "cme_internal.hpp"
+#include "cme_lean.hpp"
+
+namespace cme {
+
+// Butterflies of pass p of the wave-local transform of sign S on v (twiddles
+// t[r] = b^r of the pass), results back in v: v[q + r Qb] = Z_r of butterfly q.
+template <int N, int E, int S, int p, typename Real>
+__device__ __forceinline__ void lean_compute(cx<Real> (&v)[E], const cx<Real> *t) {
+  using PL = typename LeanPlan<N, E>::Sub;
+  constexpr int R = PL::radix(p), NSp = PL::ns(p), Qb = E / R;
+  sfor<0, Qb>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    cx<Real> z[R];
+    sfor<0, R>([&](auto ri) { z[decltype(ri)::value] = v[q + decltype(ri)::value * Qb]; });
+    if constexpr (NSp > 1) {
+      sfor<1, R>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        z[r] = ctw<S>(z[r], t[r]);
+      });
+    }
+    dft_reg<R, S>(z);
+    sfor<0, R>([&](auto ri) { v[q + decltype(ri)::value * Qb] = z[decltype(ri)::value]; });
+  });
+}
+
+// Stockham scatter of pass p (not the last) to the wave's region reg.
+template <int N, int E, int PS, int p, typename Real>
+__device__ __forceinline__ void lean_scatter(const cx<Real> (&v)[E], cx<Real> *reg, int l) {
+  using PL = typename LeanPlan<N, E>::Sub;
+  constexpr int R = PL::radix(p), NSp = PL::ns(p), Qb = E / R;
+  constexpr int T = 64;
+  sfor<0, Qb>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    const int j = l + q * T;
+    const int k = j & (NSp - 1);
+    const int b0 = lpad<PS>((j - k) * R + k);
+    sfor<0, R>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      reg[lpad_off<PS, r * NSp, NSp == 1 && R % (1 << PS) == 0>(b0)] = v[q + r * Qb];
+    });
+  });
+}
+
+template <int PS, int E, typename Real>
+__device__ __forceinline__ void lean_gather(cx<Real> (&v)[E], const cx<Real> *reg, int l) {
+  const int r0 = lpad<PS>(l);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    v[m] = reg[lpad_off<PS, m * 64, false>(r0)];
+  });
+}
+
+// Scheduling: the instructions emitted since the last full scheduling
+// barrier are ordered as NDS times (one LDS instruction, then NV VALU
+// instructions), so that one sequence's exchange drains from the LDS queue
+// while the other's butterflies execute (a wave issues in order: LDS
+// instructions bunched together stall it on the full queue).
+template <int NDS, int NV> __device__ __forceinline__ void interleave_ds_valu() {
+  sfor<0, NDS>([&](auto) {
+    __builtin_amdgcn_sched_group_barrier(0x080, 1, 0);  // DS read or write
+    __builtin_amdgcn_sched_group_barrier(0x002, NV, 0);  // VALU
+  });
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Orders a wave's LDS scatter before its gather for the compiler (the
+// hardware executes one wavefront's LDS instructions in order).  Unlike
+// wave_sync it has no wave barrier, which would end the scheduling region
+// and keep the gather from interleaving with the other sequence's VALU work.
+__device__ __forceinline__ void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Twiddles of the paired transforms, from one of two sources: LeanTw (one
+// base per pass, powers formed on use) or FullTw (every power held in
+// registers: the paired kernels run one wavefront per SIMD, so they have the
+// register file to spare and save the arithmetic).
+template <int N, int E, typename Real> struct FullTw {
+  using LP = LeanPlan<N, E>;
+  using PL = typename LP::Sub;
+  cx<Real> sub[PL::P][E];                  // pass p >= 1: b_p^r, r < radix(p)
+  cx<Real> x[(LP::WV > 1 ? LP::WV : 1)];  // b_x^r, r < WV
+};
+
+// tab[i] = exp(-2 pi i i / N), i < N
+template <int N, int E, typename Real>
+__device__ __forceinline__ void load_full_twiddles(FullTw<N, E, Real> &tw,
+                                                   const cx<Real> *__restrict__ tab, int w,
+                                                   int l) {
+  using LP = LeanPlan<N, E>;
+  using PL = typename LP::Sub;
+  constexpr int TS = LP::WV;
+  sfor<1, PL::P>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), NSp = PL::ns(p);
+    constexpr int STRIDE = LP::N1 / (NSp * R);
+    const int k = l & (NSp - 1);
+    sfor<1, R>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      tw.sub[p][r] = tab[r * k * STRIDE * TS];
+    });
+  });
+  if constexpr (LP::WV > 1) {
+    const int n1 = l + 64 * w * LP::Q;
+    sfor<1, LP::WV>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      tw.x[r] = tab[r * n1];
+    });
+  }
+}
+
+template <int N, int E, typename Real>
+__device__ __forceinline__ void load_twiddle_source(LeanTw<N, E, Real> &tw, const cx<Real> *tab,
+                                                    int w, int l) {
+  load_lean_twiddles<N, E>(tw, tab, w, l);
+}
+template <int N, int E, typename Real>
+__device__ __forceinline__ void load_twiddle_source(FullTw<N, E, Real> &tw, const cx<Real> *tab,
+                                                    int w, int l) {
+  load_full_twiddles<N, E>(tw, tab, w, l);
+}
+
+// t[r] = twiddle power r of pass p (p >= 1)
+template <int p, int R, int N, int E, typename Real>
+__device__ __forceinline__ void pass_twiddles(cx<Real> (&t)[R], const LeanTw<N, E, Real> &tw) {
+  pow_fill<R>(t, tw.sub[LeanPlan<N, E>::powoff(p)]);
+}
+template <int p, int R, int N, int E, typename Real>
+__device__ __forceinline__ void pass_twiddles(cx<Real> (&t)[R], const FullTw<N, E, Real> &tw) {
+  sfor<1, R>([&](auto ri) { t[decltype(ri)::value] = tw.sub[p][decltype(ri)::value]; });
+}
+// t[r] = power r of the cross-wave twiddle base
+template <int WV, int N, int E, typename Real>
+__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[WV], const LeanTw<N, E, Real> &tw) {
+  pow_fill<WV>(t, tw.x[0]);
+}
+template <int WV, int N, int E, typename Real>
+__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[WV], const FullTw<N, E, Real> &tw) {
+  sfor<1, WV>([&](auto ri) { t[decltype(ri)::value] = tw.x[decltype(ri)::value]; });
+}
+
+// The passes of two independent wave-local transforms of sign S, a in region
+// ra and b in region rb, software-pipelined.  On entry a has had its first
+// pass's butterflies (lean_compute<0>) and b holds its input; on exit a is
+// transformed and b still needs its last pass's butterflies.  In between, a's
+// scatter and next gather interleave with b's butterflies of the same pass,
+// and b's with a's butterflies of the next pass.
+template <int N, int E, int S, int PS, int NV, typename Real, typename TW>
+__device__ __forceinline__ void pair_passes(cx<Real> (&va)[E], cx<Real> (&vb)[E], cx<Real> *ra,
+                                            cx<Real> *rb, const TW &tw, int l) {
+  using LP = LeanPlan<N, E>;
+  using PL = typename LP::Sub;
+  sfor<0, PL::P - 1>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), R1 = PL::radix(p + 1);
+    cx<Real> t[R], t1[R1];
+    if constexpr (PL::ns(p) > 1) pass_twiddles<p>(t, tw);
+    lean_scatter<N, E, PS, p>(va, ra, l);
+    wave_fence();  // scatter before gather (other lanes' values)
+    lean_gather<PS>(va, ra, l);
+    lean_compute<N, E, S, p>(vb, t);
+    // a pass without twiddles has about half the VALU work
+    interleave_ds_valu<2 * E, (PL::ns(p) > 1 ? NV : NV / 2)>();
+    pass_twiddles<p + 1>(t1, tw);
+    lean_scatter<N, E, PS, p>(vb, rb, l);
+    wave_fence();
+    lean_gather<PS>(vb, rb, l);
+    lean_compute<N, E, S, p + 1>(va, t1);
+    interleave_ds_valu<2 * E, NV>();
+  });
+}
+
+template <int N, int E, int S, typename Real, typename TW>
+__device__ __forceinline__ void lean_compute_last(cx<Real> (&v)[E], const TW &tw) {
+  using LP = LeanPlan<N, E>;
+  using PL = typename LP::Sub;
+  constexpr int PL1 = PL::P - 1, RL = PL::radix(PL1);
+  cx<Real> tl[RL];
+  pass_twiddles<PL1>(tl, tw);
+  lean_compute<N, E, S, PL1>(v, tl);
+}
+
+// Cross-wave compute of the forward path (WV-point DFTs over n2 and
+// twiddles) for one sequence, in place in v.
+template <int N, int E, int S, typename Real>
+__device__ __forceinline__ void lean_cross_dft(cx<Real> (&v)[E],
+                                               const cx<Real> (&t)[(LeanPlan<N, E>::WV)]) {
+  using LP = LeanPlan<N, E>;
+  constexpr int WV = LP::WV, Q = LP::Q;
+  sfor<0, Q>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    cx<Real> z[WV];
+    sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[i + Q * decltype(ri)::value]; });
+    dft_reg<WV, S>(z);
+    cross_twiddle<N, E, S, i>(z, t);
+    sfor<0, WV>([&](auto ri) { v[i + Q * decltype(ri)::value] = z[decltype(ri)::value]; });
+  });
+}
+
+// Scatter of the forward path's cross-wave result to the WV regions of X.
+template <int N, int E, int PS, typename Real>
+__device__ __forceinline__ void lean_cross_scatter(const cx<Real> (&v)[E], cx<Real> *X, int c0) {
+  using LP = LeanPlan<N, E>;
+  constexpr int LB1 = LdsLen<LP::N1, PS>::value;
+  constexpr int WV = LP::WV, Q = LP::Q;
+  sfor<0, Q>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    const int n1 = lpad_off<PS, 64 * i, false>(c0);
+    sfor<0, WV>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      X[r * LB1 + n1] = v[i + Q * r];
+    });
+  });
+}
+
+// Gather of the back path's cross-wave input from the WV regions of X.
+template <int N, int E, int PS, typename Real>
+__device__ __forceinline__ void lean_cross_gather(cx<Real> (&v)[E], const cx<Real> *X, int c0) {
+  using LP = LeanPlan<N, E>;
+  constexpr int LB1 = LdsLen<LP::N1, PS>::value;
+  constexpr int WV = LP::WV, Q = LP::Q;
+  sfor<0, Q>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    const int n1 = lpad_off<PS, 64 * i, false>(c0);
+    sfor<0, WV>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      v[i + Q * r] = X[r * LB1 + n1];
+    });
+  });
+}
+
+// Cross-wave compute of the back path (twiddles, WV-point DFTs over k2).
+template <int N, int E, int S, typename Real>
+__device__ __forceinline__ void lean_cross_idft(cx<Real> (&v)[E],
+                                                const cx<Real> (&t)[(LeanPlan<N, E>::WV)]) {
+  using LP = LeanPlan<N, E>;
+  constexpr int WV = LP::WV, Q = LP::Q;
+  sfor<0, Q>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    cx<Real> z[WV];
+    sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[i + Q * decltype(ri)::value]; });
+    cross_twiddle<N, E, S, i>(z, t);
+    dft_reg<WV, S>(z);
+    sfor<0, WV>([&](auto ri) { v[i + Q * decltype(ri)::value] = z[decltype(ri)::value]; });
+  });
+}
+
+// Two forward paths (mode order in, scrambled order out) in contexts XA, XB,
+// every LDS exchange of one sequence interleaved with arithmetic of the other.
+// PRE: barrier first (single buffer set).
+template <int N, int E, int S, int PS, bool PRE, int NV, typename Real, typename TW>
+__device__ __forceinline__ void lean_fwd2(cx<Real> (&va)[E], cx<Real> (&vb)[E], cx<Real> *XA,
+                                          cx<Real> *XB, const TW &tw, int w, int l) {
+  using LP = LeanPlan<N, E>;
+  constexpr int LB1 = LdsLen<LP::N1, PS>::value;
+  constexpr int WV = LP::WV;
+  static_assert(WV > 1, "paired kernels need the cross-wave exchange");
+  if constexpr (PRE) __syncthreads();
+  cx<Real> t[WV];
+  cross_twiddles(t, tw);
+  const int c0 = lpad<PS>(l + 64 * w * LP::Q);
+  __builtin_amdgcn_sched_barrier(0);
+  lean_cross_dft<N, E, S>(va, t);
+  __builtin_amdgcn_sched_barrier(0);
+  lean_cross_scatter<N, E, PS>(va, XA, c0);
+  lean_cross_dft<N, E, S>(vb, t);
+  interleave_ds_valu<E, NV>();
+  lean_cross_scatter<N, E, PS>(vb, XB, c0);
+  __syncthreads();
+  const int r0 = w * LB1;
+  lean_gather<PS>(va, XA + r0, l);
+  __builtin_amdgcn_sched_barrier(0);
+  lean_gather<PS>(vb, XB + r0, l);
+  lean_compute<N, E, S, 0>(va, (const cx<Real> *)nullptr);
+  interleave_ds_valu<E, NV / 2>();
+  pair_passes<N, E, S, PS, NV>(va, vb, XA + r0, XB + r0, tw, l);
+  lean_compute_last<N, E, S>(vb, tw);
+}
+
+// Two back paths (scrambled order in, mode order out) in contexts XA, XB.
+template <int N, int E, int S, int PS, bool PRE, int NV, typename Real, typename TW>
+__device__ __forceinline__ void lean_back2(cx<Real> (&va)[E], cx<Real> (&vb)[E], cx<Real> *XA,
+                                           cx<Real> *XB, const TW &tw, int w, int l) {
+  using LP = LeanPlan<N, E>;
+  constexpr int LB1 = LdsLen<LP::N1, PS>::value;
+  constexpr int WV = LP::WV;
+  if constexpr (PRE) __syncthreads();
+  const int r0 = w * LB1;
+  __builtin_amdgcn_sched_barrier(0);
+  lean_compute<N, E, S, 0>(va, (const cx<Real> *)nullptr);
+  __builtin_amdgcn_sched_barrier(0);
+  pair_passes<N, E, S, PS, NV>(va, vb, XA + r0, XB + r0, tw, l);
+  // own regions: the transform's last gathers come before these scatters
+  wave_fence();
+  const int g0 = r0 + lpad<PS>(l);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    XA[lpad_off<PS, 64 * m, false>(g0)] = va[m];
+  });
+  lean_compute_last<N, E, S>(vb, tw);
+  interleave_ds_valu<E, NV>();
+  wave_fence();
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    XB[lpad_off<PS, 64 * m, false>(g0)] = vb[m];
+  });
+  __syncthreads();
+  cx<Real> t[WV];
+  cross_twiddles(t, tw);
+  const int c0 = lpad<PS>(l + 64 * w * LP::Q);
+  lean_cross_gather<N, E, PS>(va, XA, c0);
+  __builtin_amdgcn_sched_barrier(0);
+  lean_cross_gather<N, E, PS>(vb, XB, c0);
+  lean_cross_idft<N, E, S>(va, t);
+  interleave_ds_valu<E, NV>();
+  lean_cross_idft<N, E, S>(vb, t);
+}
+
+template <typename Real, int N, int E, int PS> struct DuoShape {
+  using LP = LeanPlan<N, E>;
+  static constexpr int W = LP::W;
+  static constexpr int LB1 = LdsLen<LP::N1, PS>::value;
+  static constexpr int CTX = LP::WV * LB1;  // one transform's exchange context
+  static constexpr int LIMIT = 160 * 1024;
+  static constexpr int NSET = 4 * CTX * (int)sizeof(cx<Real>) <= LIMIT ? 2 : 1;
+  static constexpr int PER_INST = NSET * 2 * CTX;
+  static constexpr int LDS_BYTES = PER_INST * (int)sizeof(cx<Real>);
+  static constexpr int THREADS = 64 * W;
+  static_assert(W > 1, "one instance spans several wavefronts");
+  static_assert(LDS_BYTES <= LIMIT, "LDS over the gfx950 per-workgroup limit");
+};
+
+// REC: record the stage inputs and inverse transforms for the adjoint
+template <typename Real, int N, int E, int PS, int NV, bool FT, bool REC>
+__global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(RunArgs a) {
+  using SH = DuoShape<Real, N, E, PS>;
+  using WP = WavePlan<N, E, 1, 0>;
+  constexpr bool ONESET = SH::NSET == 1;
+  __shared__ cx<Real> lds[SH::PER_INST];
+
+  const int lane = (int)threadIdx.x & 63;
+  const int w = (int)threadIdx.x >> 6;
+  const int id = a.order[blockIdx.x];
+  const DevInst d = a.inst[id];
+  // round parity 0 (inverse transforms) and 1 (forward transforms)
+  cx<Real> *XA0 = lds, *XB0 = lds + SH::CTX;
+  cx<Real> *XA1 = ONESET ? XA0 : lds + 2 * SH::CTX, *XB1 = ONESET ? XB0 : lds + 3 * SH::CTX;
+  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + d.offset;
+  const double *kap = a.kappa + d.offset;
+  const double *omg = a.omega + d.offset;
+
+  std::conditional_t<FT, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
+  load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+
+  cx<Real> y[E], acc[E], yt[E], keep[E], va[E], vb[E];
+  Real lr[E];
+  double om[E];
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int i = WP::mode(w, lane, m);
+    y[m] = A[i];
+    lr[m] = (Real)(-0.5 * kap[i]);
+    om[m] = omg[i];
+  });
+  const bool pump_owner = (w == 0 && lane == 0);
+  const Real gn = (Real)d.g0n;                // g0 / N, mode side
+  const Real gt = (Real)(d.g0n * (double)N);  // g0, transformed side
+  const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
+  const double h = a.h;
+  const Real hh = (Real)(0.5 * h), hf = (Real)h, h6 = (Real)(h / 6.0);
+  cx<Real> *ckpt = reinterpret_cast<cx<Real> *>(a.ckpt);
+  cx<Real> *stages = reinterpret_cast<cx<Real> *>(a.stages);
+  int32_t to_ckpt = a.ckpt_every;
+  int64_t ckpt_slot = 0;
+
+  // W = L(sig) u + p in slot m
+  auto lin = [&](const cx<Real> &u, auto mi, double sig) {
+    constexpr int m = decltype(mi)::value;
+    const Real det = (Real)(om[m] - sig);
+    cx<Real> q = {lr[m] * u.re - det * u.im, lr[m] * u.im + det * u.re};
+    if constexpr (m == E / 2) {
+      if (pump_owner) q = cadd(q, pump);
+    }
+    return q;
+  };
+  auto cube = [](const cx<Real> &x) {
+    const Real p = x.re * x.re + x.im * x.im;
+    return cx<Real>{p * x.re, p * x.im};
+  };
+  auto rec_u = [&](int64_t n, int s, auto mi, const cx<Real> &u) {
+    if constexpr (REC) {
+      constexpr int m = decltype(mi)::value;
+      stages[stage_offset(n, s, a.total) + d.offset + WP::mode(w, lane, m)] = u;
+    }
+  };
+  auto rec_a = [&](int64_t n, int s, auto mi, const cx<Real> &x) {
+    if constexpr (REC) {
+      constexpr int m = decltype(mi)::value;
+      stages[stage_offset(n, s, a.total) + a.total + d.offset + WP::tslot(w, lane, m)] = x;
+    }
+  };
+
+  for (int64_t n = 0; n < a.n_steps; ++n) {
+    const double t0 = (double)(a.step0 + n) * h;
+    const double s1 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0);
+    const double s2 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + 0.5 * h);
+    const double s4 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + h);
+    // ---- R0: Y = IDFT(y), Z_1 = IDFT(W_1)
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      rec_u(n, 0, mi, y[m]);
+      va[m] = y[m];
+      vb[m] = lin(y[m], mi, s1);
+    });
+    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      yt[m] = va[m];
+      rec_a(n, 0, mi, va[m]);
+      const cx<Real> b1 = cube(va[m]);
+      const cx<Real> a2 = {va[m].re + hh * (vb[m].re - gt * b1.im),
+                           va[m].im + hh * (vb[m].im + gt * b1.re)};
+      rec_a(n, 1, mi, a2);
+      va[m] = b1;
+      vb[m] = cube(a2);
+      keep[m] = vb[m];  // b_2, for a_3
+    });
+    // ---- R1: K'_1, K'_2
+    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> w1 = lin(y[m], mi, s1);
+      const cx<Real> k1 = {w1.re - gn * va[m].im, w1.im + gn * va[m].re};
+      const cx<Real> u2 = {y[m].re + hh * k1.re, y[m].im + hh * k1.im};
+      rec_u(n, 1, mi, u2);
+      const cx<Real> w2 = lin(u2, mi, s2);
+      const cx<Real> k2 = {w2.re - gn * vb[m].im, w2.im + gn * vb[m].re};
+      acc[m] = {k1.re + (Real)2 * k2.re, k1.im + (Real)2 * k2.im};
+      const cx<Real> u3 = {y[m].re + hh * k2.re, y[m].im + hh * k2.im};
+      rec_u(n, 2, mi, u3);
+      va[m] = w2;
+      vb[m] = lin(u3, mi, s2);
+    });
+    // ---- R2: Z_2, Z_3
+    cx<Real> w3[E];
+    sfor<0, E>([&](auto mi) { w3[decltype(mi)::value] = vb[decltype(mi)::value]; });
+    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> b2 = keep[m];
+      const cx<Real> a3 = {yt[m].re + hh * (va[m].re - gt * b2.im),
+                           yt[m].im + hh * (va[m].im + gt * b2.re)};
+      rec_a(n, 2, mi, a3);
+      const cx<Real> b3 = cube(a3);
+      const cx<Real> a4 = {yt[m].re + hf * (vb[m].re - gt * b3.im),
+                           yt[m].im + hf * (vb[m].im + gt * b3.re)};
+      rec_a(n, 3, mi, a4);
+      va[m] = b3;
+      vb[m] = cube(a4);
+    });
+    // ---- R3: K'_3, K'_4
+    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> k3 = {w3[m].re - gn * va[m].im, w3[m].im + gn * va[m].re};
+      const cx<Real> u4 = {y[m].re + hf * k3.re, y[m].im + hf * k3.im};
+      rec_u(n, 3, mi, u4);
+      const cx<Real> w4 = lin(u4, mi, s4);
+      const cx<Real> k4 = {w4.re - gn * vb[m].im, w4.im + gn * vb[m].re};
+      const cx<Real> ac = {acc[m].re + (Real)2 * k3.re + k4.re,
+                           acc[m].im + (Real)2 * k3.im + k4.im};
+      y[m] = {y[m].re + h6 * ac.re, y[m].im + h6 * ac.im};
+    });
+    if (ckpt != nullptr && --to_ckpt == 0) {
+      to_ckpt = a.ckpt_every;
+      cx<Real> *dst = ckpt + ckpt_slot * a.total + d.offset;
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        dst[WP::mode(w, lane, m)] = y[m];
+      });
+      ++ckpt_slot;
+    }
+  }
+  bool bad = false;
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    A[WP::mode(w, lane, m)] = y[m];
+    bad |= !(isfinite(y[m].re) && isfinite(y[m].im));
+  });
+  if (bad) atomicOr(&a.flags[id], 1);
+}
+
+template <typename Real, int N, int E, int PS, int NV, bool FT>
+hipError_t launch_duo_fwd(const RunArgs &a, hipStream_t st) {
+  using SH = DuoShape<Real, N, E, PS>;
+  if (a.stages)
+    hipLaunchKernelGGL((rk4_duo<Real, N, E, PS, NV, FT, true>), dim3(a.count), dim3(SH::THREADS),
+                       0, st, a);
+  else
+    hipLaunchKernelGGL((rk4_duo<Real, N, E, PS, NV, FT, false>), dim3(a.count), dim3(SH::THREADS),
+                       0, st, a);
+  return hipGetLastError();
+}
+
+// defined in cme_lean.hip: the reverse sweep over the stage records (u_s in
+// mode order, a_s in the time-domain slot order this kernel also uses)
+template <typename Real, int N, int E, int PS>
+hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
+
+// NV: VALU instructions scheduled after each LDS instruction of the other
+// sequence (reported as the variant's exchange field)
+// FT: every twiddle power held in registers (reported as exchange + 16).
+template <typename Real, int N, int E, int PS, int NV, bool FT> constexpr Variant duo_variant() {
+  using SH = DuoShape<Real, N, E, PS>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, NV + (FT ? 16 : 0), 2, 1,
+                 SH::THREADS, SH::LDS_BYTES, &launch_duo_fwd<Real, N, E, PS, NV, FT>,
+                 &launch_lean_adj<Real, N, E, PS>};
+}
+
+// The first entry of a size is its default.  N = 4096 (eight waves per
+// instance) is left to the lean kernel.
+static const Variant kDuoVariants[] = {
+    duo_variant<double, 1024, 8, 3, 4, true>(), duo_variant<double, 2048, 8, 3, 4, true>(),
+    duo_variant<double, 2048, 8, 3, 3, true>(), duo_variant<double, 2048, 8, 3, 4, false>(),
+};
+
+const Variant *variants_duo(int *count) {
+  *count = (int)(sizeof(kDuoVariants) / sizeof(kDuoVariants[0]));
+  return kDuoVariants;
+}
+
+}  // namespace cme

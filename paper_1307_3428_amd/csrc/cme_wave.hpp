@@ -40,7 +40,9 @@ template <typename Real, int N, int E, int V, int PS, int TP> struct WaveShape {
   static_assert(TP == 0 || PS == 3, "register-transpose sub-transforms use the 1-in-8 padded region");
 };
 
-template <typename Real, int N, int E, int V, int PS, int TP>
+// REC: record the stage inputs and inverse transforms for the adjoint
+// (a separate instantiation, so the plain run carries none of its code)
+template <typename Real, int N, int E, int V, int PS, int TP, bool REC>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) rk4_wave(RunArgs a) {
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   using WP = WavePlan<N, E, V, TP>;
@@ -97,7 +99,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
         if constexpr (s == 0) v[m] = y[m];
         else v[m] = {y[m].re + ch * k[m].re, y[m].im + ch * k[m].im};
       });
-      if (stages != nullptr) {
+      if constexpr (REC) {
         cx<Real> *st = stages + stage_offset(n, s, a.total) + d.offset;
         sfor<0, E>([&](auto mi) {
           constexpr int m = decltype(mi)::value;
@@ -105,8 +107,8 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
         });
       }
       fft_fwdpath<N, E, V, TP, +1, PS, !SH::TWO>(v, X, tw, w, lane);
-      if constexpr (V == 1 && TP == 0) {
-        if (stages != nullptr) {
+      if constexpr (REC && V == 1 && TP == 0) {
+        {
           cx<Real> *st = stages + stage_offset(n, s, a.total) + a.total + d.offset;
           sfor<0, E>([&](auto mi) {
             constexpr int m = decltype(mi)::value;
@@ -275,7 +277,12 @@ template <typename Real, int N, int E, int V, int PS, int TP>
 hipError_t launch_wave_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   const int grid = (a.count + SH::IPB - 1) / SH::IPB;
-  hipLaunchKernelGGL((rk4_wave<Real, N, E, V, PS, TP>), dim3(grid), dim3(SH::THREADS), 0, st, a);
+  if (a.stages)
+    hipLaunchKernelGGL((rk4_wave<Real, N, E, V, PS, TP, true>), dim3(grid), dim3(SH::THREADS), 0,
+                       st, a);
+  else
+    hipLaunchKernelGGL((rk4_wave<Real, N, E, V, PS, TP, false>), dim3(grid), dim3(SH::THREADS), 0,
+                       st, a);
   return hipGetLastError();
 }
 
