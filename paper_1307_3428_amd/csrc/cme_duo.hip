@@ -359,7 +359,7 @@ template <typename Real, int N, int E, int PS> struct DuoShape {
 };
 
 // REC: record the stage inputs and inverse transforms for the adjoint
-template <typename Real, int N, int E, int PS, int NV, bool FT, bool REC>
+template <typename Real, int N, int E, int PS, int NV, int FT, bool REC>
 __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(RunArgs a) {
   using SH = DuoShape<Real, N, E, PS>;
   using WP = WavePlan<N, E, 1, 0>;
@@ -377,7 +377,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   const double *kap = a.kappa + d.offset;
   const double *omg = a.omega + d.offset;
 
-  std::conditional_t<FT, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
+  std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> y[E], acc[E], yt[E], keep[E], va[E], vb[E];
@@ -518,7 +518,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int PS, int NV, bool FT>
+template <typename Real, int N, int E, int PS, int NV, int FT>
 hipError_t launch_duo_fwd(const RunArgs &a, hipStream_t st) {
   using SH = DuoShape<Real, N, E, PS>;
   if (a.stages)
@@ -537,10 +537,11 @@ hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
 
 // NV: VALU instructions scheduled after each LDS instruction of the other
 // sequence (reported as the variant's exchange field)
-// FT: every twiddle power held in registers (reported as exchange + 16).
-template <typename Real, int N, int E, int PS, int NV, bool FT> constexpr Variant duo_variant() {
+// FT: twiddles formed from one base per pass (0) or all powers held in
+// registers (1); reported as exchange = NV + 16 FT.
+template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant duo_variant() {
   using SH = DuoShape<Real, N, E, PS>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, NV + (FT ? 16 : 0), 2, 1,
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, NV + 16 * FT, 2, 1,
                  SH::THREADS, SH::LDS_BYTES, &launch_duo_fwd<Real, N, E, PS, NV, FT>,
                  &launch_lean_adj<Real, N, E, PS>};
 }
@@ -548,8 +549,9 @@ template <typename Real, int N, int E, int PS, int NV, bool FT> constexpr Varian
 // The first entry of a size is its default.  N = 4096 (eight waves per
 // instance) is left to the lean kernel.
 static const Variant kDuoVariants[] = {
-    duo_variant<double, 1024, 8, 3, 4, true>(), duo_variant<double, 2048, 8, 3, 4, true>(),
-    duo_variant<double, 2048, 8, 3, 3, true>(), duo_variant<double, 2048, 8, 3, 4, false>(),
+    duo_variant<double, 1024, 8, 3, 4, 1>(),
+    duo_variant<double, 2048, 8, 3, 4, 1>(),
+    duo_variant<double, 2048, 8, 3, 4, 0>(),
 };
 
 const Variant *variants_duo(int *count) {
