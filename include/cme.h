@@ -65,7 +65,7 @@ enum {
 };
 
 enum { CME_F64 = 0, CME_F32 = 1 };        /* arithmetic precision            */
-enum { CME_RK4 = 0 };                     /* integrator                      */
+enum { CME_RK4 = 0, CME_SPLIT_STEP = 2 }; /* integrator                      */
 enum { CME_FWM_CYCLIC = 0 };              /* FWM sum taken modulo N (Eq. (4)) */
 
 /* Flags of cme_init (bitwise or). */
@@ -101,7 +101,11 @@ typedef struct cme_plan cme_plan;
  *   omega  device array [total] of FP64 omega'_mu; copied likewise.
  *   precision CME_F64 or CME_F32 (FP32 state and transforms; the time and
  *          detuning bookkeeping stays FP64).
- *   integrator CME_RK4.  fwm CME_FWM_CYCLIC.
+ *   integrator CME_RK4 (classic fourth-order Runge-Kutta, Sec. 2) or
+ *          CME_SPLIT_STEP (frequency-domain Strang split-step, Sec. 2: exact
+ *          linear half steps per mode around the exact Kerr phase rotation
+ *          of the transformed field; FP64 only, N >= 128, no adjoint).
+ *          fwm CME_FWM_CYCLIC.
  *   h      step size (> 0) in the time units of kappa.
  *   stream hipStream_t the plan enqueues on (NULL: the null stream).
  *   flags  CME_INIT_* bits.
@@ -173,10 +177,11 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * transform with one workgroup barrier per transform, 2: two-level
  * transforms in four rounds of two interleaved transforms per RK4 step,
  * 3: two-level transform with twiddles rebuilt on use, sized for two
- * wavefronts per SIMD),
- * instances per workgroup, workgroup size, LDS bytes, sub-transform exchange
- * policy (0: all through LDS, 1: high lane bits in registers, low through
- * LDS).  Returns 10, or CME_EINVAL. */
+ * wavefronts per SIMD, 4: split-step map), instances per workgroup,
+ * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
+ * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
+ * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
+ * twiddles are held in registers).  Returns 10, or CME_EINVAL. */
 int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 
 /* Release the plan and everything it owns.  NULL is accepted. */

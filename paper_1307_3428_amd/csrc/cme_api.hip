@@ -32,6 +32,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_lean(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_split(&n);
+    v.insert(v.end(), a, a + n);
     a = variants_team(&n);
     v.insert(v.end(), a, a + n);
     a = variants_wave_f32(&n);
@@ -64,6 +66,7 @@ struct cme_plan {
   hipStream_t stream = nullptr;
   int32_t batch = 0;
   int32_t precision = CME_F64;
+  int32_t integrator = CME_RK4;
   double h = 0.0;
   uint32_t flags = 0;
   int64_t total = 0;
@@ -105,24 +108,32 @@ const Variant *all_variants(int *count) { return cme::variants(count); }
 // kernel is preferred where its eight wavefronts per instance fill two per
 // SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
 // per CU).
-const Variant *default_variant(int precision, int n) {
+// kind 4 kernels step the split-step map, all others RK4
+bool integrates(const Variant &v, int integrator) {
+  return (v.kind == 4) == (integrator == CME_SPLIT_STEP);
+}
+
+const Variant *default_variant(int precision, int n, int integrator) {
   int cnt = 0;
   const Variant *v = all_variants(&cnt);
   const Variant *first = nullptr;
   for (int i = 0; i < cnt; ++i) {
-    if (v[i].precision != precision || v[i].n != n) continue;
+    if (v[i].precision != precision || v[i].n != n || !integrates(v[i], integrator)) continue;
     if (v[i].kind == 3 && v[i].threads >= 512) return &v[i];
     if (!first) first = &v[i];
   }
   return first;
 }
 
-std::vector<const Variant *> candidates(int precision, int n) {
+// compiled variants for a precision and size; integrator < 0: any
+std::vector<const Variant *> candidates(int precision, int n, int integrator) {
   int cnt = 0;
   const Variant *v = all_variants(&cnt);
   std::vector<const Variant *> out;
   for (int i = 0; i < cnt; ++i)
-    if (v[i].precision == precision && v[i].n == n) out.push_back(&v[i]);
+    if (v[i].precision == precision && v[i].n == n &&
+        (integrator < 0 || integrates(v[i], integrator)))
+      out.push_back(&v[i]);
   return out;
 }
 
@@ -260,7 +271,7 @@ int autotune(cme_plan *p) {
     // the default first; another variant replaces the best so far only when
     // it is more than 5% faster, so timing noise does not flip the choice
     std::vector<const Variant *> order{c.var};
-    for (const Variant *v : candidates(p->precision, c.n))
+    for (const Variant *v : candidates(p->precision, c.n, p->integrator))
       if (v != c.var) order.push_back(v);
     for (const Variant *v : order) {
       SizeClass tmp = c;
@@ -338,7 +349,9 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   *plan = nullptr;
   if (batch <= 0 || !inst || !kappa || !omega) return CME_EINVAL;
   if (precision != CME_F64 && precision != CME_F32) return CME_EINVAL;
-  if (integrator != CME_RK4 || fwm != CME_FWM_CYCLIC) return CME_EINVAL;
+  if ((integrator != CME_RK4 && integrator != CME_SPLIT_STEP) || fwm != CME_FWM_CYCLIC)
+    return CME_EINVAL;
+  if (integrator == CME_SPLIT_STEP && precision != CME_F64) return CME_EUNSUPPORTED;
   if (!(h > 0.0) || !std::isfinite(h)) return CME_EINVAL;
   if (flags & ~(uint32_t)(CME_INIT_SKIP_STABILITY | CME_INIT_AUTOTUNE)) return CME_EINVAL;
   int64_t total = 0;
@@ -361,7 +374,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
     const double lo = std::min(x.sigma0, x.sigma1), hi = std::max(x.sigma0, x.sigma1);
     for (int64_t i = x.mode_offset; i < x.mode_offset + x.n_modes; ++i) {
       if (!std::isfinite(hk[i]) || !std::isfinite(ho[i])) return CME_ENONFINITE;
-      if (flags & CME_INIT_SKIP_STABILITY) continue;
+      if ((flags & CME_INIT_SKIP_STABILITY) || integrator != CME_RK4) continue;
       for (double sg : {lo, hi}) {
         const double zr = -0.5 * hk[i] * h, zi = (ho[i] - sg) * h;
         if (rk4_growth(zr, zi) > 1.0 + 1e-12) return CME_EUNSTABLE;
@@ -375,6 +388,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   p->stream = (hipStream_t)stream;
   p->batch = batch;
   p->precision = precision;
+  p->integrator = integrator;
   p->h = h;
   p->flags = flags;
   p->total = total;
@@ -418,7 +432,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
     SizeClass c;
     c.n = g.first;
     c.ids = g.second;
-    c.var = default_variant(precision, c.n);
+    c.var = default_variant(precision, c.n, integrator);
     if (!c.var) {
       rc = CME_EUNSUPPORTED;
       break;
@@ -472,7 +486,7 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
                 double *g_kappa, double *g_ain) {
   if (!p || !A0 || !gA_T || step0 < 0 || n_steps < 0 || ckpt_every < 0) return CME_EINVAL;
   if (ckpt && ckpt_every == 0) return CME_EINVAL;
-  if (p->precision != CME_F64) return CME_EUNSUPPORTED;
+  if (p->precision != CME_F64 || p->integrator != CME_RK4) return CME_EUNSUPPORTED;
   for (auto &c : p->classes)
     if (!c.var->adj) return CME_EUNSUPPORTED;
   const size_t vec = p->elem * (size_t)p->total;
@@ -558,7 +572,7 @@ int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t kernel_id) {
   for (auto &c : p->classes) {
     if (c.n != n_modes) continue;
     if (kernel_id < 0 || kernel_id >= cnt || v[kernel_id].n != n_modes ||
-        v[kernel_id].precision != p->precision)
+        v[kernel_id].precision != p->precision || !integrates(v[kernel_id], p->integrator))
       return CME_EUNSUPPORTED;
     c.var = &v[kernel_id];
     return CME_OK;
@@ -567,7 +581,7 @@ int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t kernel_id) {
 }
 
 int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t cap) {
-  const auto c = candidates(precision, n_modes);
+  const auto c = candidates(precision, n_modes, -1);
   for (size_t i = 0; i < c.size() && (int32_t)i < cap; ++i)
     if (ids) ids[i] = variant_id(c[i]);
   return (int32_t)c.size();

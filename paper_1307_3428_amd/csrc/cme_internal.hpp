@@ -86,7 +86,7 @@ struct Variant {
   int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel
                    // (cme_wave.hpp), 2: four rounds of two interleaved transforms
                    // per RK4 step (cme_duo.hip), 3: two-level kernel sized for two
-                   // waves per SIMD (cme_lean.hip)
+                   // waves per SIMD (cme_lean.hip), 4: split-step map (cme_split.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -99,6 +99,7 @@ const Variant *variants_wave(int *count);      // cme_wave.hip (FP64)
 const Variant *variants_wave_f32(int *count);  // cme_wave_f32.hip
 const Variant *variants_lean(int *count);  // cme_lean.hip
 const Variant *variants_duo(int *count);   // cme_duo.hip
+const Variant *variants_split(int *count); // cme_split.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 }  // namespace cme

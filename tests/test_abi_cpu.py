@@ -70,21 +70,22 @@ def _inst(n=64, offset=0, **kw):
                             d["sigma1"], d["tau_ramp"])
 
 
-def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan=True):
+def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan=True,
+              integrator=0):
     lib = C.load_library()
     handle = ctypes.c_void_p(12345)
     kp = kappa.ctypes.data_as(ctypes.c_void_p) if kappa is not None else None
     op = omega.ctypes.data_as(ctypes.c_void_p) if omega is not None else None
     rc = lib.cme_init(ctypes.byref(handle) if plan else None,
-                      len(inst) if batch is None else batch, inst, kp, op, precision, 0, 0, h,
-                      None, flags)
+                      len(inst) if batch is None else batch, inst, kp, op, precision, integrator,
+                      0, h, None, flags)
     return rc, handle.value
 
 
 @pytest.mark.parametrize("case", ["null_plan", "batch0", "null_kappa", "bad_n", "n_too_big",
                                   "n_too_small", "neg_h", "nan_h", "bad_precision",
                                   "reserved", "neg_offset", "overlap", "bad_flags",
-                                  "nan_sigma", "neg_kext"])
+                                  "nan_sigma", "neg_kext", "bad_integrator", "split_fp32"])
 def test_init_rejects_invalid_arguments_without_a_device(case):
     kappa = np.ones(256)
     omega = np.zeros(256)
@@ -123,6 +124,12 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
         expect = C.CME_ENONFINITE
     elif case == "neg_kext":
         inst = _inst(kappa_ext=-0.1)
+    elif case == "bad_integrator":
+        kw["integrator"] = 1
+    elif case == "split_fp32":
+        kw["integrator"] = C.CME_SPLIT_STEP
+        kw["precision"] = C.CME_F32
+        expect = C.CME_EUNSUPPORTED
     rc, handle = _init_raw(inst, kappa, omega, **kw)
     assert rc == expect, (case, rc)
     if kw.get("plan", True):

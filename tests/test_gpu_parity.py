@@ -64,7 +64,7 @@ def _variant_params():
     try:
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
-                for k in C.cme_list_kernels(C.CME_F64, n)]
+                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] != 4]
     except Exception:
         return [(16, 0)]
 
@@ -375,3 +375,70 @@ def test_concurrent_classes_match_separate_plans(cme):
         yq, _ = gpu_run(cme, q, 0.005, 20)
         for j, i in enumerate(idx):
             assert np.array_equal(y[p.slice(i)], yq[q.slice(j)]), (n, i)
+
+
+# ---------------------------------------------------------------------------
+# Split-step map (CME_SPLIT_STEP) against the oracle's split-step map.
+# ---------------------------------------------------------------------------
+def _split_params():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096)
+                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] == 4]
+    except Exception:
+        return [(128, 0)]
+
+
+@pytest.mark.parametrize("n,kid", _split_params())
+def test_split_step_variant_matches_oracle(cme, orc, n, kid):
+    import torch
+    info = cme.cme_kernel_info(kid)
+    print(f"variant {info['name']}", flush=True)
+    batch = 5 if info["instances_per_group"] > 1 else 2
+    p = W.pack(moderate_batch(5000 + n, [n] * batch))
+    steps, h = 20, 0.01
+    with cme.Plan(p, h, integrator=cme.CME_SPLIT_STEP) as plan:
+        plan.select(n, kid)
+        A = plan.state(p.a0)
+        plan.run(A, steps, step0=3)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        assert not plan.status().any()
+    ref = orc.split_step_run(p, h, steps, step0=3)
+    errs = per_instance_err(p, y, ref)
+    assert max(errs) <= 1e-12, errs
+
+
+def test_split_step_fig1_ensemble(cme, orc):
+    """The paper's Fig. 1 set (N = 256, four pump levels) with the split-step
+    map over 500 steps of h = 1e-3, all four in one launch."""
+    import torch
+    wl = W.fig1_ensemble(n_steps=500, h=1e-3)
+    p = W.pack(wl.instances)
+    with cme.Plan(p, wl.h, integrator=cme.CME_SPLIT_STEP) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, wl.n_steps)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+    ref = orc.split_step_run(p, wl.h, wl.n_steps)
+    errs = per_instance_err(p, y, ref)
+    print("fig1 split-step rel err", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) <= 1e-10, errs
+
+
+def test_split_step_checkpoints_and_split_runs(cme):
+    import torch
+    p = W.pack(moderate_batch(13, [256, 2048, 128]))
+    with cme.Plan(p, 0.01, integrator=cme.CME_SPLIT_STEP) as plan:
+        A = plan.state(p.a0)
+        ck = torch.zeros((2, p.total), dtype=torch.complex128, device="cuda")
+        plan.run(A, 20, ckpt_every=10, ckpt=ck)
+        B = plan.state(p.a0)
+        plan.run(B, 10)
+        torch.cuda.synchronize()
+        assert torch.equal(ck[0], B)
+        plan.run(B, 10, step0=10)
+        torch.cuda.synchronize()
+        assert torch.equal(ck[1], B) and torch.equal(A, B)
+        with pytest.raises(cme.CmeError):
+            plan.adjoint(plan.state(p.a0), plan.state(p.a0), 5)
