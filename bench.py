@@ -22,7 +22,11 @@ Also reported on the same JSON line:
   fp32          the same sweep in FP32 (FP64 time bookkeeping);
   uneven        the uneven-octave batch (512 instances, N in {1024, ..., 8192},
                 h = 2e-4, 2e4 steps) in FP64 and FP32, classic RK4 on the
-                instances it is stable for (the excluded count is reported).
+                instances it is stable for (the excluded count is reported);
+  fig1          the paper's Fig. 1 ensemble (four N = 256 runs to normalised
+                time 128 pi) with the split-step map in one launch, beside
+                the paper's own 54 s (desktop CPU, split-step; its step size
+                is not stated, h = 1e-3 here).
 """
 import argparse
 import hashlib
@@ -37,9 +41,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "mode-steps/s (FP64, 1 GPU) at ≤1e-10 rel. error vs oracle; adjoint/forward ratio"
 FP64_PEAK_TFLOPS = 78.6
-COUNTERS = os.path.join(ROOT, "profiles", "rk4_wave_sweep_n2048_counters.txt")
-KERNEL_SOURCES = ("cme_fft.hpp", "cme_internal.hpp", "cme_wave.hpp", "cme_wave.hip", "cme_lean.hip",
-                  "cme_kernels.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "rk4_duo_sweep_n2048_counters.txt")
+# sources of the default N = 2048 kernel (rk4_duo)
+KERNEL_SOURCES = ("cme_fft.hpp", "cme_internal.hpp", "cme_lean.hpp", "cme_duo.hip")
 
 
 def kernel_source_hash() -> str:
@@ -230,6 +234,7 @@ def main() -> int:
         out["single"] = single_leg(C, W, torch)
         out["fp32"] = fp32_leg(C, W, torch, rk_steps)
         out["uneven"] = uneven_leg(C, W, torch)
+        out["fig1"] = fig1_leg(C, W, torch)
     print(json.dumps(out))
     return 0
 
@@ -315,6 +320,25 @@ def uneven_leg(C, W, torch, steps=20000):
             out[name] = {"mode_steps_per_s": p.total * steps / s, "seconds": s,
                          "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
     return out
+
+
+def fig1_leg(C, W, torch):
+    """Fig. 1 ensemble, full horizon, split-step (CME_SPLIT_STEP), FP64."""
+    wl = W.fig1_ensemble()
+    p = W.pack(wl.instances)
+    with C.Plan(p, wl.h, integrator=C.CME_SPLIT_STEP) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 100)
+        torch.cuda.synchronize()
+        A = plan.state(p.a0)
+        s = timed_run(plan, A, wl.n_steps, torch)
+        finite = not plan.status().any()
+        k = plan.kernel(256)["name"]
+    return {"workload": f"fig1_ensemble: 4 x N=256, {wl.n_steps} split-step steps of h={wl.h} "
+                        "(tau = 256 pi, normalised time 128 pi)",
+            "seconds": s, "mode_steps_per_s": p.total * wl.n_steps / s, "kernel": k,
+            "all_finite": bool(finite),
+            "paper": "54 s for the four runs on a desktop CPU (Fig. 1 caption); step not stated"}
 
 
 def single_leg(C, W, torch):
