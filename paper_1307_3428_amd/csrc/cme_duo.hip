@@ -518,6 +518,200 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
+// Reverse sweep over one checkpoint segment, paired like the forward step.
+// With ybar' the cotangent of the step's output, kbar_s = w_s h ybar' +
+// c_{s+1} h ubar_{s+1}, and ubar_s = conj(L_s) kbar_s + DFT(q_s), where
+// q_s = 2 |a_s|^2 z_s + a_s^2 conj(z_s), z_s = IDFT(-i (g0/N) kbar_s) (the
+// transpose of the Kerr term's derivative at a_s = IDFT(u_s)).  By
+// linearity, IDFT(ubar_s) = IDFT(conj(L_s) kbar_s) + N q_s, so with
+// Ybar = IDFT(ybar') and P_s = IDFT(conj(L_s) kbar_s):
+//   z_{s-1} = -i (g0/N) (w_{s-1} h Ybar + c_s h (P_s + N q_s)),
+// and a step takes four rounds of two transforms:
+//   A: Ybar, P_4             -> z_4, q_4, z_3, q_3
+//   B: DFT q_4, q_3          -> ubar_4, kbar_3, ubar_3, kbar_2
+//   C: IDFT(ubar_3), P_2     -> z_2, q_2, z_1, q_1
+//   D: DFT q_2, q_1          -> ubar_2, kbar_1, ubar_1;  ybar = ybar' + sum ubar_s
+// (round C transforms ubar_3 itself, which is known by then: IDFT(ubar_3) =
+// P_3 + N q_3).
+// Parameter cotangents per stage: gbar_omega += Re(conj(kbar) i u),
+// gbar_kappa -= Re(conj(kbar) u) / 2, gbar_Ain += sqrt(kappa_ext) kbar at
+// mu = 0.  The stage records (u_s in mode order, a_s in the time-domain
+// slot order) are loaded a round before they are needed.
+template <typename Real, int N, int E, int PS, int NV, int FT>
+__global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_reverse(AdjArgs a) {
+  using SH = DuoShape<Real, N, E, PS>;
+  using WP = WavePlan<N, E, 1, 0>;
+  constexpr bool ONESET = SH::NSET == 1;
+  __shared__ cx<Real> lds[SH::PER_INST];
+
+  const int lane = (int)threadIdx.x & 63;
+  const int w = (int)threadIdx.x >> 6;
+  const int id = a.order[blockIdx.x];
+  const DevInst d = a.inst[id];
+  cx<Real> *XA0 = lds, *XB0 = lds + SH::CTX;
+  cx<Real> *XA1 = ONESET ? XA0 : lds + 2 * SH::CTX, *XB1 = ONESET ? XB0 : lds + 3 * SH::CTX;
+  const double *kap = a.kappa + d.offset;
+  const double *omg = a.omega + d.offset;
+  cx<Real> *gA = reinterpret_cast<cx<Real> *>(a.gA) + d.offset;
+  const cx<Real> *stages = reinterpret_cast<const cx<Real> *>(a.stages);
+
+  std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
+  load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+
+  cx<Real> yb1[E], yb[E], ybt[E], k2[E], va[E], vb[E], ra[E], rb[E];
+  Real lr[E], gom[E], gka[E];
+  double om[E];
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int i = WP::mode(w, lane, m);
+    yb1[m] = gA[i];
+    lr[m] = (Real)(-0.5 * kap[i]);
+    om[m] = omg[i];
+    gom[m] = (Real)0;
+    gka[m] = (Real)0;
+  });
+  const bool pump_owner = (w == 0 && lane == 0);
+  cx<Real> gain = {(Real)0, (Real)0};
+  const Real gn = (Real)d.g0n, nn_r = (Real)N;
+  const double h = a.h;
+  const Real hw1 = (Real)(h / 6.0), hw2 = (Real)(h / 3.0), hh = (Real)(0.5 * h), hf = (Real)h;
+
+  // conj(L(sig)) k in slot m
+  auto clin = [&](const cx<Real> &k, auto mi, double sig) {
+    constexpr int m = decltype(mi)::value;
+    const Real det = (Real)(om[m] - sig);
+    return cx<Real>{lr[m] * k.re + det * k.im, lr[m] * k.im - det * k.re};
+  };
+  // -i (g0/N) x
+  auto mig = [&](const cx<Real> &x) { return cx<Real>{gn * x.im, -gn * x.re}; };
+  // 2 |a|^2 z + a^2 conj(z)
+  auto kerr_t = [](const cx<Real> &z, const cx<Real> &av) {
+    const Real p2 = (Real)2 * (av.re * av.re + av.im * av.im);
+    const cx<Real> a2 = {av.re * av.re - av.im * av.im, (Real)2 * av.re * av.im};
+    return cx<Real>{p2 * z.re + a2.re * z.re + a2.im * z.im,
+                    p2 * z.im + a2.im * z.re - a2.re * z.im};
+  };
+  auto grads = [&](auto mi, const cx<Real> &kv, const cx<Real> &u) {
+    constexpr int m = decltype(mi)::value;
+    gom[m] += kv.im * u.re - kv.re * u.im;
+    gka[m] -= (Real)0.5 * (kv.re * u.re + kv.im * u.im);
+    if constexpr (m == E / 2) {
+      if (pump_owner) gain = cadd(gain, kv);
+    }
+  };
+  // record addresses are rebuilt at each use (an opaque base) rather than
+  // kept in registers for the whole run
+  auto load_a = [&](cx<Real> (&dst)[E], int64_t n, int s) {
+    const cx<Real> *rec = stages + stage_offset(n, s, a.total) + a.total + d.offset;
+    int base = WP::tslot(w, lane, 0);
+    asm volatile("" : "+v"(base));
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      dst[m] = rec[base + (WP::tslot(w, lane, m) - WP::tslot(w, lane, 0))];
+    });
+  };
+  auto load_u = [&](cx<Real> (&dst)[E], int64_t n, int s) {
+    const cx<Real> *rec = stages + stage_offset(n, s, a.total) + d.offset;
+    int base = WP::mode(w, lane, 0);
+    asm volatile("" : "+v"(base));
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      dst[m] = rec[base + (WP::mode(w, lane, m) - WP::mode(w, lane, 0))];
+    });
+  };
+
+  for (int nn = a.n_seg - 1; nn >= 0; --nn) {
+    const double t0 = (double)(a.step_first + nn) * h;
+    const double s1 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0);
+    const double s2 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + 0.5 * h);
+    const double s4 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + h);
+    // ---- A: Ybar = IDFT(ybar'), P_4 = IDFT(conj(L_4) kbar_4), kbar_4 = h/6 ybar'
+    load_a(ra, nn, 3);
+    load_a(rb, nn, 2);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      va[m] = yb1[m];
+      vb[m] = clin(cx<Real>{hw1 * yb1[m].re, hw1 * yb1[m].im}, mi, s4);
+    });
+    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      ybt[m] = va[m];
+      const cx<Real> q4 = kerr_t(mig(cx<Real>{hw1 * va[m].re, hw1 * va[m].im}), ra[m]);
+      const cx<Real> x3 = {hw2 * va[m].re + hf * (vb[m].re + nn_r * q4.re),
+                           hw2 * va[m].im + hf * (vb[m].im + nn_r * q4.im)};
+      va[m] = q4;
+      vb[m] = kerr_t(mig(x3), rb[m]);
+    });
+    // ---- B: DFT(q_4), DFT(q_3)
+    load_u(ra, nn, 3);
+    load_u(rb, nn, 2);
+    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> k4 = {hw1 * yb1[m].re, hw1 * yb1[m].im};
+      const cx<Real> c4 = clin(k4, mi, s4);
+      const cx<Real> ub4 = {c4.re + va[m].re, c4.im + va[m].im};
+      grads(mi, k4, ra[m]);
+      const cx<Real> k3 = {hw2 * yb1[m].re + hf * ub4.re, hw2 * yb1[m].im + hf * ub4.im};
+      const cx<Real> c3 = clin(k3, mi, s2);
+      const cx<Real> ub3 = {c3.re + vb[m].re, c3.im + vb[m].im};
+      grads(mi, k3, rb[m]);
+      yb[m] = {yb1[m].re + ub4.re + ub3.re, yb1[m].im + ub4.im + ub3.im};
+      k2[m] = {hw2 * yb1[m].re + hh * ub3.re, hw2 * yb1[m].im + hh * ub3.im};
+      va[m] = ub3;
+      vb[m] = clin(k2[m], mi, s2);
+    });
+    // ---- C: IDFT(ubar_3) = P_3 + N q_3, P_2
+    load_a(ra, nn, 1);
+    load_a(rb, nn, 0);
+    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> x2 = {hw2 * ybt[m].re + hh * va[m].re, hw2 * ybt[m].im + hh * va[m].im};
+      const cx<Real> q2 = kerr_t(mig(x2), ra[m]);
+      const cx<Real> x1 = {hw1 * ybt[m].re + hh * (vb[m].re + nn_r * q2.re),
+                           hw1 * ybt[m].im + hh * (vb[m].im + nn_r * q2.im)};
+      va[m] = q2;
+      vb[m] = kerr_t(mig(x1), rb[m]);
+    });
+    // ---- D: DFT(q_2), DFT(q_1)
+    load_u(ra, nn, 1);
+    load_u(rb, nn, 0);
+    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> c2 = clin(k2[m], mi, s2);
+      const cx<Real> ub2 = {c2.re + va[m].re, c2.im + va[m].im};
+      grads(mi, k2[m], ra[m]);
+      const cx<Real> k1 = {hw1 * yb1[m].re + hh * ub2.re, hw1 * yb1[m].im + hh * ub2.im};
+      const cx<Real> c1 = clin(k1, mi, s1);
+      const cx<Real> ub1 = {c1.re + vb[m].re, c1.im + vb[m].im};
+      grads(mi, k1, rb[m]);
+      yb1[m] = {yb[m].re + ub2.re + ub1.re, yb[m].im + ub2.im + ub1.im};
+    });
+  }
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int i = WP::mode(w, lane, m);
+    gA[i] = yb1[m];
+    if (a.g_omega) a.g_omega[d.offset + i] += (double)gom[m];
+    if (a.g_kappa) a.g_kappa[d.offset + i] += (double)gka[m];
+  });
+  if (pump_owner && a.g_ain) {
+    a.g_ain[2 * id] += d.sqrt_kext * (double)gain.re;
+    a.g_ain[2 * id + 1] += d.sqrt_kext * (double)gain.im;
+  }
+}
+
+template <typename Real, int N, int E, int PS, int NV, int FT>
+hipError_t launch_duo_adj(const AdjArgs &a, hipStream_t st) {
+  using SH = DuoShape<Real, N, E, PS>;
+  hipLaunchKernelGGL((rk4_duo_reverse<Real, N, E, PS, NV, FT>), dim3(a.count), dim3(SH::THREADS),
+                     0, st, a);
+  return hipGetLastError();
+}
+
 template <typename Real, int N, int E, int PS, int NV, int FT>
 hipError_t launch_duo_fwd(const RunArgs &a, hipStream_t st) {
   using SH = DuoShape<Real, N, E, PS>;
@@ -538,12 +732,14 @@ hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
 // NV: VALU instructions scheduled after each LDS instruction of the other
 // sequence (reported as the variant's exchange field)
 // FT: twiddles formed from one base per pass (0) or all powers held in
-// registers (1); reported as exchange = NV + 16 FT.
+// registers (1); reported as exchange = NV + 16 FT.  The reverse sweep has
+// more live state and always forms its twiddles (it reads the stage records
+// in the same slot order whatever the forward kernel's twiddle source).
 template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant duo_variant() {
   using SH = DuoShape<Real, N, E, PS>;
   return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, NV + 16 * FT, 2, 1,
                  SH::THREADS, SH::LDS_BYTES, &launch_duo_fwd<Real, N, E, PS, NV, FT>,
-                 &launch_lean_adj<Real, N, E, PS>};
+                 &launch_duo_adj<Real, N, E, PS, NV, 0>};
 }
 
 // The first entry of a size is its default.  N = 4096 (eight waves per
