@@ -23,6 +23,8 @@ Also reported on the same JSON line:
   uneven        the uneven-octave batch (512 instances, N in {1024, ..., 8192},
                 h = 2e-4, 2e4 steps) in FP64 and FP32, classic RK4 on the
                 instances it is stable for (the excluded count is reported);
+  padded        256 instances of N = 1024 with the alias-free truncated sum
+                (2N-point transforms) beside the cyclic sum, 2000 steps;
   fig1          the paper's Fig. 1 ensemble (four N = 256 runs to normalised
                 time 128 pi) with the split-step map in one launch, beside
                 the paper's own 54 s (desktop CPU, split-step; its step size
@@ -235,6 +237,7 @@ def main() -> int:
         out["fp32"] = fp32_leg(C, W, torch, rk_steps)
         out["uneven"] = uneven_leg(C, W, torch)
         out["fig1"] = fig1_leg(C, W, torch)
+        out["padded"] = padded_leg(C, W, torch)
     print(json.dumps(out))
     return 0
 
@@ -319,6 +322,21 @@ def uneven_leg(C, W, torch, steps=20000):
             s = timed_run(plan, A, steps, torch)
             out[name] = {"mode_steps_per_s": p.total * steps / s, "seconds": s,
                          "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
+    return out
+
+
+def padded_leg(C, W, torch, steps=2000):
+    """256 x N=1024 (seeded random parameters): padded vs cyclic FWM sum."""
+    insts = W.random_batch(41, [1024] * 256, noise=1e-3)
+    p = W.pack(insts)
+    out = {"workload": f"256 x N=1024 random instances, {steps} RK4 steps of h=1e-3"}
+    for fwm, name in ((C.CME_FWM_PADDED, "padded"), (C.CME_FWM_CYCLIC, "cyclic")):
+        with C.Plan(p, 1e-3, fwm=fwm) as plan:
+            A = plan.state(p.a0)
+            plan.run(A, 100)
+            torch.cuda.synchronize()
+            s = timed_run(plan, A, steps, torch)
+            out[name] = {"mode_steps_per_s": p.total * steps / s, "kernel": plan.kernel(1024)["name"]}
     return out
 
 

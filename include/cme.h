@@ -66,7 +66,13 @@ enum {
 
 enum { CME_F64 = 0, CME_F32 = 1 };        /* arithmetic precision            */
 enum { CME_RK4 = 0, CME_SPLIT_STEP = 2 }; /* integrator                      */
-enum { CME_FWM_CYCLIC = 0 };              /* FWM sum taken modulo N (Eq. (4)) */
+enum {
+  CME_FWM_CYCLIC = 0, /* FWM sum taken modulo N (Eq. (4))                       */
+  CME_FWM_PADDED = 1  /* FWM sum over the instance's own modes only (the literal
+                         Kronecker delta of Eq. (2)), computed on 2N-point
+                         transforms with the upper half held at zero; RK4,
+                         FP64, N = 128 ... 4096, no adjoint                  */
+};
 
 /* Flags of cme_init (bitwise or). */
 enum {
@@ -105,7 +111,7 @@ typedef struct cme_plan cme_plan;
  *          CME_SPLIT_STEP (frequency-domain Strang split-step, Sec. 2: exact
  *          linear half steps per mode around the exact Kerr phase rotation
  *          of the transformed field; FP64 only, N >= 128, no adjoint).
- *          fwm CME_FWM_CYCLIC.
+ *   fwm    CME_FWM_CYCLIC or CME_FWM_PADDED (see above).
  *   h      step size (> 0) in the time units of kappa.
  *   stream hipStream_t the plan enqueues on (NULL: the null stream).
  *   flags  CME_INIT_* bits.
@@ -177,7 +183,8 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * transform with one workgroup barrier per transform, 2: two-level
  * transforms in four rounds of two interleaved transforms per RK4 step,
  * 3: two-level transform with twiddles rebuilt on use, sized for two
- * wavefronts per SIMD, 4: split-step map), instances per workgroup,
+ * wavefronts per SIMD, 4: split-step map, 5: RK4 with the padded sum on
+ * N-point transforms for instances of N/2 modes), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all

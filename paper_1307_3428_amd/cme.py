@@ -23,7 +23,7 @@ CME_OK, CME_EINVAL, CME_ENOMEM, CME_EHIP = 0, -1, -2, -3
 CME_EUNSTABLE, CME_ENONFINITE, CME_EUNSUPPORTED, CME_ENODEVICE = -4, -5, -6, -7
 CME_F64, CME_F32 = 0, 1
 CME_RK4, CME_SPLIT_STEP = 0, 2
-CME_FWM_CYCLIC = 0
+CME_FWM_CYCLIC, CME_FWM_PADDED = 0, 1
 CME_INIT_DEFAULT, CME_INIT_SKIP_STABILITY, CME_INIT_AUTOTUNE = 0, 1, 2
 
 EXPORTED = (
@@ -210,7 +210,7 @@ def cme_kernel_info(kernel_id: int) -> dict:
     info = dict(zip(KERNEL_INFO_FIELDS, (int(x) for x in out)))
     info["id"] = int(kernel_id)
     info["threads_per_instance"] = info["n_modes"] // info["elems_per_thread"]
-    info["name"] = ({0: "rk4_persistent", 1: "rk4_wave", 2: "rk4_duo", 3: "rk4_lean", 4: "split_lean"}[info["kind"]]
+    info["name"] = ({0: "rk4_persistent", 1: "rk4_wave", 2: "rk4_duo", 3: "rk4_lean", 4: "split_lean", 5: "rk4_wave_pad"}[info["kind"]]
                     + "<{},{},{},{},{}{}>".format(
                         "double" if info["precision"] == 0 else "float", info["n_modes"],
                         info["elems_per_thread"], info["sub_transforms"], info["pad_shift"],
@@ -233,7 +233,8 @@ class Plan:
     (numpy arrays, as workloads.pack returns)."""
 
     def __init__(self, packed, h: float, precision: int = CME_F64, flags: int = CME_INIT_DEFAULT,
-                 device: str = "cuda", stream=None, integrator: int = CME_RK4):
+                 device: str = "cuda", stream=None, integrator: int = CME_RK4,
+                 fwm: int = CME_FWM_CYCLIC):
         import torch
         self.torch = torch
         self.batch = int(packed.batch)
@@ -247,7 +248,7 @@ class Plan:
         kappa = torch.as_tensor(np.ascontiguousarray(packed.kappa, np.float64), device=self.device)
         omega = torch.as_tensor(np.ascontiguousarray(packed.omega, np.float64), device=self.device)
         self.handle = cme_init(self._inst, kappa, omega, self.h, precision=precision,
-                               integrator=integrator, stream=stream, flags=flags)
+                               integrator=integrator, fwm=fwm, stream=stream, flags=flags)
 
     def state(self, a0) -> "object":
         """A device tensor of the plan's complex dtype holding a0 (packed)."""

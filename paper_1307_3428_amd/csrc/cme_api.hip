@@ -34,6 +34,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_split(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_pad(&n);
+    v.insert(v.end(), a, a + n);
     a = variants_team(&n);
     v.insert(v.end(), a, a + n);
     a = variants_wave_f32(&n);
@@ -67,6 +69,7 @@ struct cme_plan {
   int32_t batch = 0;
   int32_t precision = CME_F64;
   int32_t integrator = CME_RK4;
+  int32_t fwm = CME_FWM_CYCLIC;
   double h = 0.0;
   uint32_t flags = 0;
   int64_t total = 0;
@@ -108,9 +111,13 @@ const Variant *all_variants(int *count) { return cme::variants(count); }
 // kernel is preferred where its eight wavefronts per instance fill two per
 // SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
 // per CU).
-// kind 4 kernels step the split-step map, all others RK4
+// kind 4 kernels step the split-step map, kind 5 RK4 with the padded sum,
+// all others RK4 with the cyclic sum; `integrator` encodes both choices as
+// integrator + 16 fwm
 bool integrates(const Variant &v, int integrator) {
-  return (v.kind == 4) == (integrator == CME_SPLIT_STEP);
+  const int fwm = integrator >> 4, integ = integrator & 15;
+  if (fwm == CME_FWM_PADDED) return v.kind == 5;
+  return v.kind != 5 && (v.kind == 4) == (integ == CME_SPLIT_STEP);
 }
 
 const Variant *default_variant(int precision, int n, int integrator) {
@@ -271,7 +278,7 @@ int autotune(cme_plan *p) {
     // the default first; another variant replaces the best so far only when
     // it is more than 5% faster, so timing noise does not flip the choice
     std::vector<const Variant *> order{c.var};
-    for (const Variant *v : candidates(p->precision, c.n, p->integrator))
+    for (const Variant *v : candidates(p->precision, c.n, p->integrator + 16 * p->fwm))
       if (v != c.var) order.push_back(v);
     for (const Variant *v : order) {
       SizeClass tmp = c;
@@ -349,9 +356,12 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   *plan = nullptr;
   if (batch <= 0 || !inst || !kappa || !omega) return CME_EINVAL;
   if (precision != CME_F64 && precision != CME_F32) return CME_EINVAL;
-  if ((integrator != CME_RK4 && integrator != CME_SPLIT_STEP) || fwm != CME_FWM_CYCLIC)
+  if ((integrator != CME_RK4 && integrator != CME_SPLIT_STEP) ||
+      (fwm != CME_FWM_CYCLIC && fwm != CME_FWM_PADDED))
     return CME_EINVAL;
   if (integrator == CME_SPLIT_STEP && precision != CME_F64) return CME_EUNSUPPORTED;
+  if (fwm == CME_FWM_PADDED && (precision != CME_F64 || integrator != CME_RK4))
+    return CME_EUNSUPPORTED;
   if (!(h > 0.0) || !std::isfinite(h)) return CME_EINVAL;
   if (flags & ~(uint32_t)(CME_INIT_SKIP_STABILITY | CME_INIT_AUTOTUNE)) return CME_EINVAL;
   int64_t total = 0;
@@ -389,50 +399,73 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   p->batch = batch;
   p->precision = precision;
   p->integrator = integrator;
+  p->fwm = fwm;
   p->h = h;
   p->flags = flags;
   p->total = total;
   p->elem = precision == CME_F64 ? 16 : 8;
   p->inst.assign(inst, inst + batch);
 
+  // Padded plans run each instance of N modes on a 2N-point transform: the
+  // plan keeps kappa / omega' per transform point (the instance's values in
+  // the middle half, kappa = 1, omega' = 0 elsewhere, where the kernels hold
+  // the field at zero) and addresses the caller's state separately.
+  const bool pad = fwm == CME_FWM_PADDED;
+  const int tf = pad ? 2 : 1;  // transform points per mode
   std::vector<DevInst> dv((size_t)batch);
+  std::vector<double> pk, po;
+  int64_t ptotal = 0;
   for (int32_t b = 0; b < batch; ++b) {
     const cme_instance &x = inst[b];
     const double sk = std::sqrt(x.kappa_ext);
+    const int nt = tf * x.n_modes;
     DevInst &d = dv[b];
-    d.offset = x.mode_offset;
+    d.offset = pad ? ptotal : x.mode_offset;
+    d.a_offset = x.mode_offset;
     d.pump_re = sk * x.a_in_re;
     d.pump_im = sk * x.a_in_im;
-    d.g0n = x.g0 / (double)x.n_modes;
+    d.g0n = x.g0 / (double)nt;
     d.sqrt_kext = sk;
     d.sigma0 = x.sigma0;
     d.sigma1 = x.sigma1;
     d.tau_ramp = x.tau_ramp;
-    d.n = x.n_modes;
+    d.n = nt;
     d.reserved = 0;
+    if (pad) {
+      pk.resize((size_t)(ptotal + nt), 1.0);
+      po.resize((size_t)(ptotal + nt), 0.0);
+      for (int i = 0; i < x.n_modes; ++i) {
+        pk[(size_t)(ptotal + x.n_modes / 2 + i)] = hk[(size_t)(x.mode_offset + i)];
+        po[(size_t)(ptotal + x.n_modes / 2 + i)] = ho[(size_t)(x.mode_offset + i)];
+      }
+    }
+    ptotal += nt;
   }
+  const int64_t ktotal = pad ? ptotal : total;
+  const double *kh = pad ? pk.data() : hk.data(), *oh = pad ? po.data() : ho.data();
   rc = CME_OK;
   if (hipMalloc((void **)&p->d_inst, sizeof(DevInst) * batch) != hipSuccess ||
-      hipMalloc((void **)&p->d_kappa, sizeof(double) * total) != hipSuccess ||
-      hipMalloc((void **)&p->d_omega, sizeof(double) * total) != hipSuccess ||
+      hipMalloc((void **)&p->d_kappa, sizeof(double) * ktotal) != hipSuccess ||
+      hipMalloc((void **)&p->d_omega, sizeof(double) * ktotal) != hipSuccess ||
       hipMalloc((void **)&p->d_flags, sizeof(int32_t) * batch) != hipSuccess)
     rc = CME_ENOMEM;
   if (rc == CME_OK &&
       (hipMemcpy(p->d_inst, dv.data(), sizeof(DevInst) * batch, hipMemcpyHostToDevice) != hipSuccess ||
-       hipMemcpy(p->d_kappa, hk.data(), sizeof(double) * total, hipMemcpyHostToDevice) != hipSuccess ||
-       hipMemcpy(p->d_omega, ho.data(), sizeof(double) * total, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_kappa, kh, sizeof(double) * ktotal, hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(p->d_omega, oh, sizeof(double) * ktotal, hipMemcpyHostToDevice) != hipSuccess ||
        hipMemset(p->d_flags, 0, sizeof(int32_t) * batch) != hipSuccess))
     rc = CME_EHIP;
 
-  // size classes, largest first (longest work first when they share the chip)
+  // size classes (by transform length), largest first (longest work first
+  // when they share the chip)
   std::map<int, std::vector<int32_t>, std::greater<int>> groups;
-  for (int32_t b = 0; b < batch; ++b) groups[inst[b].n_modes].push_back(b);
+  for (int32_t b = 0; b < batch; ++b) groups[tf * inst[b].n_modes].push_back(b);
   for (auto &g : groups) {
     if (rc != CME_OK) break;
     SizeClass c;
     c.n = g.first;
     c.ids = g.second;
-    c.var = default_variant(precision, c.n, integrator);
+    c.var = default_variant(precision, c.n, integrator + 16 * fwm);
     if (!c.var) {
       rc = CME_EUNSUPPORTED;
       break;
@@ -486,7 +519,8 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
                 double *g_kappa, double *g_ain) {
   if (!p || !A0 || !gA_T || step0 < 0 || n_steps < 0 || ckpt_every < 0) return CME_EINVAL;
   if (ckpt && ckpt_every == 0) return CME_EINVAL;
-  if (p->precision != CME_F64 || p->integrator != CME_RK4) return CME_EUNSUPPORTED;
+  if (p->precision != CME_F64 || p->integrator != CME_RK4 || p->fwm != CME_FWM_CYCLIC)
+    return CME_EUNSUPPORTED;
   for (auto &c : p->classes)
     if (!c.var->adj) return CME_EUNSUPPORTED;
   const size_t vec = p->elem * (size_t)p->total;
@@ -555,10 +589,15 @@ int cme_status(cme_plan *p, int32_t *flags) {
   return CME_OK;
 }
 
+// size class of an instance size (padded plans: twice the modes)
+int class_size(const cme_plan *p, int32_t n_modes) {
+  return p->fwm == CME_FWM_PADDED ? 2 * n_modes : n_modes;
+}
+
 int cme_plan_kernel(const cme_plan *p, int32_t n_modes, int32_t *kernel_id) {
   if (!p || !kernel_id) return CME_EINVAL;
   for (const auto &c : p->classes) {
-    if (c.n != n_modes) continue;
+    if (c.n != class_size(p, n_modes)) continue;
     *kernel_id = variant_id(c.var);
     return CME_OK;
   }
@@ -570,9 +609,10 @@ int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t kernel_id) {
   int cnt = 0;
   const Variant *v = all_variants(&cnt);
   for (auto &c : p->classes) {
-    if (c.n != n_modes) continue;
-    if (kernel_id < 0 || kernel_id >= cnt || v[kernel_id].n != n_modes ||
-        v[kernel_id].precision != p->precision || !integrates(v[kernel_id], p->integrator))
+    if (c.n != class_size(p, n_modes)) continue;
+    if (kernel_id < 0 || kernel_id >= cnt || v[kernel_id].n != c.n ||
+        v[kernel_id].precision != p->precision ||
+        !integrates(v[kernel_id], p->integrator + 16 * p->fwm))
       return CME_EUNSUPPORTED;
     c.var = &v[kernel_id];
     return CME_OK;

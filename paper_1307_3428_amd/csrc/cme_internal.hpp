@@ -16,6 +16,8 @@ struct DevInst {
   double sigma0, sigma1, tau_ramp;
   int32_t n;
   int32_t reserved;
+  int64_t a_offset;    // first element in the caller's packed state (padded plans:
+                       // the state has n/2 modes per instance, kappa/omega' n)
 };
 
 // Arguments of one persistent forward launch over one size class.
@@ -86,7 +88,8 @@ struct Variant {
   int kind;        // 0: team kernel (cme_kernels.hip), 1: two-level wave kernel
                    // (cme_wave.hpp), 2: four rounds of two interleaved transforms
                    // per RK4 step (cme_duo.hip), 3: two-level kernel sized for two
-                   // waves per SIMD (cme_lean.hip), 4: split-step map (cme_split.hip)
+                   // waves per SIMD (cme_lean.hip), 4: split-step map (cme_split.hip),
+                   // 5: RK4 with the padded (alias-free truncated) sum (cme_wave.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -96,6 +99,7 @@ struct Variant {
 
 const Variant *variants_team(int *count);  // cme_kernels.hip
 const Variant *variants_wave(int *count);      // cme_wave.hip (FP64)
+const Variant *variants_pad(int *count);       // cme_wave.hip (padded sum)
 const Variant *variants_wave_f32(int *count);  // cme_wave_f32.hip
 const Variant *variants_lean(int *count);  // cme_lean.hip
 const Variant *variants_duo(int *count);   // cme_duo.hip

@@ -16,6 +16,19 @@ static const Variant kWaveVariants[] = {
     wave_variant<double, 8192, 16, 2, 3, 1>(), wave_variant<double, 8192, 16, 2, 3>(),
 };
 
+// Alias-free truncated sum (CME_FWM_PADDED): instances of N/2 = 128 ... 4096
+// modes on N-point transforms.
+static const Variant kPadVariants[] = {
+    pad_variant<double, 256, 4, 1, 2>(),  pad_variant<double, 512, 8, 1, 3>(),
+    pad_variant<double, 1024, 8, 1, 3>(), pad_variant<double, 2048, 8, 1, 3>(),
+    pad_variant<double, 4096, 8, 1, 3>(), pad_variant<double, 8192, 16, 2, 3>(),
+};
+
+const Variant *variants_pad(int *count) {
+  *count = (int)(sizeof(kPadVariants) / sizeof(kPadVariants[0]));
+  return kPadVariants;
+}
+
 const Variant *variants_wave(int *count) {
   *count = (int)(sizeof(kWaveVariants) / sizeof(kWaveVariants[0]));
   return kWaveVariants;

@@ -41,8 +41,13 @@ template <typename Real, int N, int E, int V, int PS, int TP> struct WaveShape {
 };
 
 // REC: record the stage inputs and inverse transforms for the adjoint
-// (a separate instantiation, so the plain run carries none of its code)
-template <typename Real, int N, int E, int V, int PS, int TP, bool REC>
+// (a separate instantiation, so the plain run carries none of its code).
+// PAD: alias-free truncated sum -- the instance's N/2 modes sit in the middle
+// of this N-point transform (transform index i <-> mode i - N/4 of the
+// caller's state), the other half stays zero (its derivative is masked), so
+// the cyclic sum of Eq. (4) over 2x padding equals the literal sum of Eq. (2)
+// over the instance's own modes.
+template <typename Real, int N, int E, int V, int PS, int TP, bool REC, bool PAD = false>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) rk4_wave(RunArgs a) {
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   using WP = WavePlan<N, E, V, TP>;
@@ -61,7 +66,12 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
   const DevInst d = a.inst[id];
   cx<Real> *X = lds + sub * SH::PER_INST;
   cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;
-  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + d.offset;
+  static_assert(!(PAD && REC), "padded plans have no adjoint");
+  constexpr int Q4 = N / 4;
+  // caller's state of this instance, and where transform index i lives in it
+  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + (PAD ? d.a_offset : d.offset);
+  auto in_band = [](int i) { return !PAD || (i >= Q4 && i < 3 * Q4); };
+  auto phys = [](int i) { return PAD ? i - Q4 : i; };
   const double *kap = a.kappa + d.offset;
   const double *omg = a.omega + d.offset;
 
@@ -71,10 +81,12 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
   cx<Real> y[E], k[E], acc[E], v[E];
   Real lr[E];
   double om[E];
+  bool band[E];
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
     const int i = WP::mode(w, lane, m);
-    y[m] = A[i];
+    band[m] = in_band(i);
+    y[m] = band[m] ? A[phys(i)] : cx<Real>{(Real)0, (Real)0};
     lr[m] = (Real)(-0.5 * kap[i]);
     om[m] = omg[i];
     k[m] = {(Real)0, (Real)0};
@@ -133,6 +145,9 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
         if constexpr (m == E / 2) {
           if (pump_owner) kn = cadd(kn, pump);
         }
+        if constexpr (PAD) {
+          if (!band[m]) kn = {(Real)0, (Real)0};
+        }
         k[m] = kn;
         if constexpr (s == 0) acc[m] = kn;
         else {
@@ -148,10 +163,11 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
     });
     if (ckpt != nullptr && --to_ckpt == 0) {
       to_ckpt = a.ckpt_every;
-      cx<Real> *dst = ckpt + ckpt_slot * a.total + d.offset;
+      cx<Real> *dst = ckpt + ckpt_slot * a.total + (PAD ? d.a_offset : d.offset);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
-        dst[WP::mode(w, lane, m)] = y[m];
+        const int i = WP::mode(w, lane, m);
+        if (band[m]) dst[phys(i)] = y[m];
       });
       ++ckpt_slot;
     }
@@ -159,7 +175,8 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) r
   bool bad = false;
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    A[WP::mode(w, lane, m)] = y[m];
+    const int i = WP::mode(w, lane, m);
+    if (band[m]) A[phys(i)] = y[m];
     bad |= !(isfinite(y[m].re) && isfinite(y[m].im));
   });
   if (bad) atomicOr(&a.flags[id], 1);
@@ -293,6 +310,22 @@ hipError_t launch_wave_adj(const AdjArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((rk4_wave_reverse<Real, N, E, V, PS, TP>), dim3(grid), dim3(SH::THREADS), 0,
                      st, a);
   return hipGetLastError();
+}
+
+template <typename Real, int N, int E, int V, int PS, int TP>
+hipError_t launch_wave_pad(const RunArgs &a, hipStream_t st) {
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  const int grid = (a.count + SH::IPB - 1) / SH::IPB;
+  hipLaunchKernelGGL((rk4_wave<Real, N, E, V, PS, TP, false, true>), dim3(grid), dim3(SH::THREADS),
+                     0, st, a);
+  return hipGetLastError();
+}
+
+// Padded-sum variant (kind 5): transform size N for instances of N/2 modes.
+template <typename Real, int N, int E, int V, int PS, int TP = 0> constexpr Variant pad_variant() {
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, TP, 5, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES, &launch_wave_pad<Real, N, E, V, PS, TP>, nullptr};
 }
 
 // defined in cme_lean.hip (FP64, E = 8, PS = 3): the reverse sweep that

@@ -71,21 +71,22 @@ def _inst(n=64, offset=0, **kw):
 
 
 def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan=True,
-              integrator=0):
+              integrator=0, fwm=0):
     lib = C.load_library()
     handle = ctypes.c_void_p(12345)
     kp = kappa.ctypes.data_as(ctypes.c_void_p) if kappa is not None else None
     op = omega.ctypes.data_as(ctypes.c_void_p) if omega is not None else None
     rc = lib.cme_init(ctypes.byref(handle) if plan else None,
                       len(inst) if batch is None else batch, inst, kp, op, precision, integrator,
-                      0, h, None, flags)
+                      fwm, h, None, flags)
     return rc, handle.value
 
 
 @pytest.mark.parametrize("case", ["null_plan", "batch0", "null_kappa", "bad_n", "n_too_big",
                                   "n_too_small", "neg_h", "nan_h", "bad_precision",
                                   "reserved", "neg_offset", "overlap", "bad_flags",
-                                  "nan_sigma", "neg_kext", "bad_integrator", "split_fp32"])
+                                  "nan_sigma", "neg_kext", "bad_integrator", "split_fp32",
+                                  "bad_fwm", "padded_split"])
 def test_init_rejects_invalid_arguments_without_a_device(case):
     kappa = np.ones(256)
     omega = np.zeros(256)
@@ -126,6 +127,12 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
         inst = _inst(kappa_ext=-0.1)
     elif case == "bad_integrator":
         kw["integrator"] = 1
+    elif case == "bad_fwm":
+        kw["fwm"] = 2
+    elif case == "padded_split":
+        kw["fwm"] = C.CME_FWM_PADDED
+        kw["integrator"] = C.CME_SPLIT_STEP
+        expect = C.CME_EUNSUPPORTED
     elif case == "split_fp32":
         kw["integrator"] = C.CME_SPLIT_STEP
         kw["precision"] = C.CME_F32

@@ -64,7 +64,8 @@ def _variant_params():
     try:
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
-                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] != 4]
+                for k in C.cme_list_kernels(C.CME_F64, n)
+                if C.cme_kernel_info(k)["kind"] not in (4, 5)]
     except Exception:
         return [(16, 0)]
 
@@ -442,3 +443,56 @@ def test_split_step_checkpoints_and_split_runs(cme):
         assert torch.equal(ck[1], B) and torch.equal(A, B)
         with pytest.raises(cme.CmeError):
             plan.adjoint(plan.state(p.a0), plan.state(p.a0), 5)
+
+
+# ---------------------------------------------------------------------------
+# Alias-free truncated sum (CME_FWM_PADDED) against the oracle's truncated
+# sum (the literal Kronecker delta of Eq. (2), pinned by enumeration).
+# ---------------------------------------------------------------------------
+def _pad_params():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(n // 2, k) for n in (256, 512, 1024, 2048, 4096, 8192)
+                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] == 5]
+    except Exception:
+        return [(128, 0)]
+
+
+@pytest.mark.parametrize("n,kid", _pad_params())
+def test_padded_variant_matches_truncated_oracle(cme, orc, n, kid):
+    import torch
+    info = cme.cme_kernel_info(kid)
+    print(f"variant {info['name']} for N = {n}", flush=True)
+    batch = 5 if info["instances_per_group"] > 1 else 2
+    p = W.pack(moderate_batch(7000 + n, [n] * batch))
+    with cme.Plan(p, 0.01, fwm=cme.CME_FWM_PADDED) as plan:
+        plan.select(n, kid)
+        A = plan.state(p.a0)
+        plan.run(A, 4, step0=5)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        assert not plan.status().any()
+    ref, _ = orc.run(p, 0.01, 4, step0=5, truncated=True)
+    cyc, _ = orc.run(p, 0.01, 4, step0=5)
+    errs = per_instance_err(p, y, ref)
+    assert max(errs) <= 1e-12, errs
+    # the truncated and the cyclic sums really differ on these states
+    assert min(per_instance_err(p, cyc, ref)) > 1e-6
+
+
+def test_padded_mixed_sizes_longer_horizon(cme, orc):
+    import torch
+    p = W.pack(moderate_batch(71, [128, 512, 256, 1024]))
+    with cme.Plan(p, 0.005, fwm=cme.CME_FWM_PADDED) as plan:
+        A = plan.state(p.a0)
+        ck = torch.zeros((2, p.total), dtype=torch.complex128, device="cuda")
+        plan.run(A, 200, ckpt_every=100, ckpt=ck)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        assert torch.equal(ck[1], A)
+        with pytest.raises(cme.CmeError):
+            plan.adjoint(plan.state(p.a0), plan.state(p.a0), 3)
+    ref, _ = orc.run(p, 0.005, 200, truncated=True)
+    errs = per_instance_err(p, y, ref)
+    print("padded 200 steps rel err", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) <= 1e-10, errs
