@@ -1,0 +1,245 @@
+"""LLE cross-check: the cyclic CME against the time-domain LLE (Sec. 2).
+
+The coupled mode equations with the cyclic four-wave-mixing sum are the
+Fourier-collocation discretisation of a driven, damped NLS equation in the
+fast time; with kappa_mu and omega'_mu even polynomials in mu the time-domain
+equation is a PDE with a scalar Kerr term (tests/lle_timedomain.py).  Since
+psi = T A is linear and constant in time, classic RK4 on psi is T times RK4 on
+A, and the time-domain Strang split-step (exact linear part through a matrix
+exponential, exact Kerr phase rotation pointwise in theta) is T times the
+frequency-domain split-step of Sec. 2.  Both therefore agree with the mode
+space solvers to rounding, which is what these tests hold them to.
+
+CPU tests check the oracle against the LLE; GPU tests check the HIP solver
+against it.  The per-mode loss tests exercise a frequency-dependent
+absorption-plus-coupling profile (Sec. 3 names it as a convenience of the
+coupled mode form) on every integrator and both sums against the oracle.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1307_3428_amd import workloads as W
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import lle_timedomain as L  # noqa: E402
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def start_state(rng, res: L.LLE, level: float = 0.3) -> np.ndarray:
+    """Homogeneous lower-branch state plus full-support noise, in the time domain."""
+    cw = W.cw_state(res.a_in, res.sigma0, 0.0, res.kappa0, res.g0, res.kappa_ext)
+    noise = (rng.standard_normal(res.n) + 1j * rng.standard_normal(res.n)) * (level / math.sqrt(2.0))
+    return cw + noise
+
+
+def as_instance(res: L.LLE, psi0: np.ndarray) -> W.Instance:
+    """The same resonator in mode space (centred storage)."""
+    return W.Instance(n_modes=res.n, kappa=res.kappa_modes(), omega=res.omega_modes(),
+                      kappa_ext=res.kappa_ext, g0=res.g0, a_in=res.a_in, sigma0=res.sigma0,
+                      sigma1=res.sigma1, tau_ramp=res.tau_ramp, a0=L.to_modes(psi0))
+
+
+# ---------------------------------------------------------------------------
+# the time-domain model itself
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [8, 16, 64])
+def test_second_derivative_matrix_differentiates_trig_polynomials(n):
+    """Closed-form second derivatives of a random real trig polynomial of
+    full bandwidth, Nyquist term cos(N theta / 2) included."""
+    rng = np.random.default_rng(n)
+    th = L.theta_grid(n)
+    c = rng.standard_normal(n // 2 + 1)
+    s = rng.standard_normal(n // 2)
+    f = sum(c[k] * np.cos(k * th) for k in range(n // 2 + 1)) \
+        + sum(s[k] * np.sin(k * th) for k in range(1, n // 2))
+    f2 = sum(-k * k * c[k] * np.cos(k * th) for k in range(n // 2 + 1)) \
+        + sum(-k * k * s[k] * np.sin(k * th) for k in range(1, n // 2))
+    got = L.second_derivative_matrix(n) @ f
+    assert np.abs(got - f2).max() <= 1e-13 * (n / 2) ** 2 * np.abs(np.r_[c, s]).sum()
+
+
+def test_lle_split_step_is_second_order():
+    """Strang splitting: halving h cuts the error against a fine RK4 by 4."""
+    rng = np.random.default_rng(7)
+    res = L.random_resonator(rng, 32, ramp=False)
+    psi0 = start_state(rng, res)
+    T = 0.2
+    ref = res.rk4(psi0, 1e-4, 2000)
+    errs = [rel_err(res.split_step(psi0, T / k, k), ref) for k in (25, 50, 100)]
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    print("split-step errors", errs, "orders", rates)
+    assert all(1.9 < r < 2.1 for r in rates)
+
+
+# ---------------------------------------------------------------------------
+# oracle (mode space, direct FWM sum) vs LLE (time domain, pointwise Kerr)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,steps,h", [(16, 300, 2e-3), (64, 300, 2e-3), (128, 150, 2e-3)])
+def test_oracle_rk4_is_the_lle_rk4(orc, n, steps, h):
+    rng = np.random.default_rng(100 + n)
+    res = L.random_resonator(rng, n)
+    psi0 = start_state(rng, res)
+    p = W.pack([as_instance(res, psi0)])
+    y_orc, _ = orc.run(p, h, steps)
+    y_lle = L.to_modes(res.rk4(psi0, h, steps))
+    err = rel_err(y_orc, y_lle)
+    moved = rel_err(p.a0, y_lle)
+    print(f"N={n}: oracle vs LLE {err:.2e} (state moved by {moved:.2e})")
+    assert moved > 1e-2
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n,steps,h", [(16, 300, 2e-3), (64, 200, 2e-3)])
+def test_oracle_split_step_is_the_lle_split_step(orc, n, steps, h):
+    rng = np.random.default_rng(200 + n)
+    res = L.random_resonator(rng, n)
+    res.tau_ramp = 40 * h
+    psi0 = start_state(rng, res)
+    p = W.pack([as_instance(res, psi0)])
+    y_orc = orc.split_step_run(p, h, steps)
+    y_lle = L.to_modes(res.split_step(psi0, h, steps))
+    err = rel_err(y_orc, y_lle)
+    print(f"N={n}: oracle split-step vs LLE split-step {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_nonuniform_loss_is_not_a_scalar_lle(orc):
+    """Negative control: with quadratic loss the LLE needs the diffusive
+    operator; dropping it (a scalar-loss LLE) leaves a visible difference."""
+    rng = np.random.default_rng(5)
+    res = L.random_resonator(rng, 32, kappa2=0.01)
+    psi0 = start_state(rng, res)
+    p = W.pack([as_instance(res, psi0)])
+    y_orc, _ = orc.run(p, 2e-3, 200)
+    flat = L.LLE(
+        n=res.n, kappa0=res.kappa0, kappa2=0.0, d2=res.d2, d4=res.d4, kappa_ext=res.kappa_ext,
+        a_in=res.a_in, g0=res.g0, sigma0=res.sigma0, sigma1=res.sigma1, tau_ramp=res.tau_ramp)
+    y_flat = L.to_modes(flat.rk4(psi0, 2e-3, 200))
+    y_full = L.to_modes(res.rk4(psi0, 2e-3, 200))
+    assert rel_err(y_orc, y_full) <= 1e-12
+    assert rel_err(y_orc, y_flat) > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# GPU (HIP solver through the C ABI) vs LLE
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cme():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1307_3428_amd import cme as C
+    C.load_library()
+    return C
+
+
+def gpu_run(C, packed, h, steps, **plan_kw):
+    import torch
+    with C.Plan(packed, h, **plan_kw) as plan:
+        A = plan.state(packed.a0)
+        plan.run(A, steps)
+        torch.cuda.synchronize()
+        assert not np.any(plan.status())
+        names = {int(n): plan.kernel(int(n))["name"] for n in set(packed.n_modes.tolist())}
+        return A.cpu().numpy(), names
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,steps", [(64, 300), (256, 200), (1024, 100), (2048, 60)])
+def test_gpu_rk4_is_the_lle_rk4(cme, n, steps):
+    """The default kernel for each size (N = 2048: the batched headline
+    kernel), two resonators per plan."""
+    h = 1e-3
+    rng = np.random.default_rng(300 + n)
+    ress = [L.random_resonator(rng, n) for _ in range(2)]
+    psis = [start_state(rng, r) for r in ress]
+    p = W.pack([as_instance(r, s) for r, s in zip(ress, psis)])
+    y, names = gpu_run(cme, p, h, steps)
+    for b, (r, s) in enumerate(zip(ress, psis)):
+        ref = L.to_modes(r.rk4(s, h, steps))
+        err = rel_err(y[p.slice(b)], ref)
+        print(f"N={n} {names[n]} resonator {b}: GPU vs LLE {err:.2e}", flush=True)
+        assert err <= 1e-11
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,steps", [(128, 300), (256, 200), (512, 100)])
+def test_gpu_split_step_is_the_lle_split_step(cme, n, steps):
+    h = 2e-3
+    rng = np.random.default_rng(400 + n)
+    ress = [L.random_resonator(rng, n) for _ in range(2)]
+    for r in ress:
+        r.tau_ramp = 20 * h
+    psis = [start_state(rng, r) for r in ress]
+    p = W.pack([as_instance(r, s) for r, s in zip(ress, psis)])
+    y, names = gpu_run(cme, p, h, steps, integrator=cme.CME_SPLIT_STEP)
+    for b, (r, s) in enumerate(zip(ress, psis)):
+        ref = L.to_modes(r.split_step(s, h, steps))
+        err = rel_err(y[p.slice(b)], ref)
+        print(f"N={n} {names[n]} resonator {b}: GPU split-step vs LLE {err:.2e}", flush=True)
+        assert err <= 1e-11
+
+
+# ---------------------------------------------------------------------------
+# frequency-dependent absorption + coupling (GPU vs oracle)
+# ---------------------------------------------------------------------------
+
+def profile_batch(seed, sizes):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        inst = W.profile_instance(n, rng)
+        out.append(inst)
+    return out
+
+
+def test_profile_instance_loss_is_absorption_plus_coupling():
+    rng = np.random.default_rng(3)
+    inst = W.profile_instance(256, rng)
+    mu = W.mu_grid(256)
+    assert np.all(inst.kappa > 0)
+    # the pump mode's loss holds the coupling that carries the pump in
+    assert inst.kappa[128] > inst.kappa_ext
+    # absorption rises toward both band edges, coupling falls with mu:
+    # the loss is not even in mu, so no scalar-loss LLE describes it
+    assert inst.kappa[0] != inst.kappa[-1]
+    assert abs(mu[0]) == 128
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("integrator,fwm", [("rk4", "cyclic"), ("rk4", "padded"), ("split", "cyclic")])
+def test_gpu_profile_losses_match_oracle(cme, orc, integrator, fwm):
+    sizes = [256, 512, 1024, 2048] if fwm == "cyclic" else [256, 512, 1024]
+    if integrator == "split":
+        sizes = [256, 512, 1024]
+    p = W.pack(profile_batch(77, sizes))
+    h, steps = 2e-3, 100
+    kw = {}
+    if integrator == "split":
+        kw["integrator"] = cme.CME_SPLIT_STEP
+    if fwm == "padded":
+        kw["fwm"] = cme.CME_FWM_PADDED
+    y, names = gpu_run(cme, p, h, steps, **kw)
+    if integrator == "split":
+        ref = orc.split_step_run(p, h, steps)
+    else:
+        ref, _ = orc.run(p, h, steps, truncated=(fwm == "padded"))
+    for b in range(p.batch):
+        g, r = y[p.slice(b)], ref[p.slice(b)]
+        n = int(p.n_modes[b])
+        err = rel_err(g, r)
+        # the sidebands alone (the pump mode dominates the norm)
+        side = np.arange(n) != n // 2
+        err_side = rel_err(g[side], r[side])
+        print(f"{integrator}/{fwm} N={n} {names[n]}: GPU vs oracle {err:.2e}, sidebands {err_side:.2e} "
+              f"(sideband power {np.sum(np.abs(r[side]) ** 2):.2e})", flush=True)
+        assert err <= 1e-11 and err_side <= 1e-10
