@@ -23,6 +23,9 @@ Also reported on the same JSON line:
   uneven        the uneven-octave batch (512 instances, N in {1024, ..., 8192},
                 h = 2e-4, 2e4 steps) in FP64 and FP32, classic RK4 on the
                 instances it is stable for (the excluded count is reported);
+  staged        the four-step transforms through global memory: 128 x N=8192
+                (beside the LDS-resident kernels), 64 x N=16384, 16 x N=65536,
+                with algorithmic HBM GB/s;
   padded        256 instances of N = 1024 with the alias-free truncated sum
                 (2N-point transforms) beside the cyclic sum, 2000 steps;
   fig1          the paper's Fig. 1 ensemble (four N = 256 runs to normalised
@@ -238,6 +241,7 @@ def main() -> int:
         out["uneven"] = uneven_leg(C, W, torch)
         out["fig1"] = fig1_leg(C, W, torch)
         out["padded"] = padded_leg(C, W, torch)
+        out["staged"] = staged_leg(C, W, torch)
     print(json.dumps(out))
     return 0
 
@@ -322,6 +326,40 @@ def uneven_leg(C, W, torch, steps=20000):
             s = timed_run(plan, A, steps, torch)
             out[name] = {"mode_steps_per_s": p.total * steps / s, "seconds": s,
                          "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
+    return out
+
+
+# HBM bytes per mode and RK4 step of the staged kernels: per stage the
+# column kernel reads S and y (+ u, acc after the first stage) and kappa,
+# omega' and writes S (+ u, acc; y at the last stage); the row kernel reads
+# and writes S.  16 B per complex value, 8 per real.
+STAGED_BYTES_PER_MODE_STEP = (16 * 5 + 16) + 2 * (16 * 7 + 16) + (16 * 6 + 16) + 4 * 32
+
+
+def staged_leg(C, W, torch):
+    """The staged path (four-step transforms through global memory): FP64,
+    N = 8192 against the LDS-resident kernel, and N = 16384 / 65536, where it
+    is the only kernel; about 10^6 modes per plan (seeded random instances,
+    RK4 h = 2e-4)."""
+    out = {"bytes_per_mode_step": STAGED_BYTES_PER_MODE_STEP, "peak_GBps": 8000.0, "cases": []}
+    for n, b, steps in ((8192, 128, 200), (16384, 64, 200), (65536, 16, 100)):
+        p = W.pack(W.random_batch(43, [n] * b, noise=1e-3))
+        ids = [k for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] in (1, 6)]
+        for kid in ids:
+            with C.Plan(p, 2e-4) as plan:
+                plan.select(n, kid)
+                A = plan.state(p.a0)
+                plan.run(A, 10)
+                torch.cuda.synchronize()
+                s = timed_run(plan, A, steps, torch)
+                name = plan.kernel(n)["name"]
+            rate = p.total * steps / s
+            case = {"workload": f"{b} x N={n}, {steps} RK4 steps", "kernel": name,
+                    "mode_steps_per_s": rate, "us_per_step": 1e6 * s / steps}
+            if name.startswith("rk4_staged"):
+                gbps = rate * STAGED_BYTES_PER_MODE_STEP / 1e9
+                case.update({"algorithmic_GBps": gbps, "frac_hbm_peak": gbps / 8000.0})
+            out["cases"].append(case)
     return out
 
 

@@ -23,7 +23,8 @@
  *   - An instance is one resonator.  Its N mode amplitudes are stored
  *     contiguously in centred order: element i holds mode mu = i - N/2, so the
  *     pump mode mu = 0 is element N/2.  N must be a power of two,
- *     16 <= N <= 8192.
+ *     16 <= N <= 65536; above 8192 only FP64 RK4 with the cyclic sum is
+ *     supported (CME_EUNSUPPORTED otherwise).
  *   - A batch packs instances back to back; instance b starts at element
  *     inst[b].mode_offset of every per-mode array (state, kappa, omega').
  *     Ranges of different instances must not overlap.  "total" below is the
@@ -84,7 +85,7 @@ enum {
 
 /* One resonator: the scalar symbols of Eq. (1). */
 typedef struct {
-  int32_t n_modes;      /* N: power of two, 16 <= N <= 8192                   */
+  int32_t n_modes;      /* N: power of two, 16 <= N <= 65536                  */
   int32_t reserved;     /* must be 0                                          */
   int64_t mode_offset;  /* first element of this instance in per-mode arrays  */
   double kappa_ext;     /* external coupling loss kappa_ext >= 0              */
@@ -126,7 +127,11 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst,
 int cme_step(cme_plan *plan, void *A, int64_t step0);
 
 /* Advance A by n_steps >= 0 RK4 steps starting at step index step0 >= 0.
- * Each instance stays on one GPU workgroup for the whole call (persistent).
+ * Each instance stays on one GPU workgroup for the whole call (persistent),
+ * except for N >= 16384 (and N = 8192 when the staged variant is selected):
+ * there the transforms are four-step transforms with the transpose through
+ * global memory, each instance spans several workgroups, a step is eight
+ * launches, and the plan owns a workspace of 3 N complex values per instance.
  *   ckpt_every  0, or store the state after every ckpt_every steps into
  *   ckpt        device complex [n_steps / ckpt_every][total]: slot j holds
  *               A after (j + 1) * ckpt_every steps of this call. */
@@ -145,7 +150,10 @@ int cme_run(cme_plan *plan, void *A, int64_t step0, int64_t n_steps,
  * ckpt: device complex [n_steps / ckpt_every][total] as written by cme_run
  * with the same step0 / ckpt_every, or NULL (the adjoint then runs the
  * forward pass itself).  A0 is not modified.  Uses plan-owned device scratch
- * of 4 * ckpt_every * total complex values (allocated on first use). */
+ * of 8 * ckpt_every * total complex values (allocated on first use).  FP64
+ * RK4 with the cyclic sum and N <= 8192 only (CME_EUNSUPPORTED otherwise); a
+ * size running the staged variant recomputes and reverses with a variant of
+ * the same size that has a reverse sweep. */
 int cme_adjoint(cme_plan *plan, const void *A0, const void *ckpt, int64_t step0,
                 int64_t n_steps, int32_t ckpt_every, const void *gA_T, void *gA_0,
                 double *g_omega, double *g_kappa, double *g_ain);
@@ -184,7 +192,9 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * transforms in four rounds of two interleaved transforms per RK4 step,
  * 3: two-level transform with twiddles rebuilt on use, sized for two
  * wavefronts per SIMD, 4: split-step map, 5: RK4 with the padded sum on
- * N-point transforms for instances of N/2 modes), instances per workgroup,
+ * N-point transforms for instances of N/2 modes, 6: four-step transforms
+ * staged through global memory, several workgroups per instance, with the
+ * row length N1 in the V field), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all

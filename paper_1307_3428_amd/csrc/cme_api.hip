@@ -40,6 +40,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_wave_f32(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_staged(&n);
+    v.insert(v.end(), a, a + n);
     return v;
   }();
   *count = (int)all.size();
@@ -59,6 +61,9 @@ struct SizeClass {
   // and joined back into the caller's stream with events
   hipStream_t side = nullptr;
   hipEvent_t done = nullptr;
+  // workspace of the staged variants (grown when such a variant is chosen)
+  void *d_work = nullptr;
+  size_t work_bytes = 0;
 };
 
 }  // namespace
@@ -196,6 +201,22 @@ int grow(void **p, size_t *have, size_t need) {
   return CME_OK;
 }
 
+// workspace a variant needs for a class, allocated before it first runs
+int ensure_work(const cme_plan *p, SizeClass &c, const Variant *v) {
+  if (v->work == 0) return CME_OK;
+  return grow(&c.d_work, &c.work_bytes,
+              p->elem * (size_t)v->work * (size_t)c.n * c.ids.size());
+}
+
+// the variant a class uses for the adjoint: its own if that has a reverse
+// sweep, else the first compiled variant of its size that has one
+const Variant *adjoint_variant(const cme_plan *p, const SizeClass &c) {
+  if (c.var->adj) return c.var;
+  for (const Variant *v : candidates(p->precision, c.n, p->integrator + 16 * p->fwm))
+    if (v->adj) return v;
+  return nullptr;
+}
+
 void free_plan(cme_plan *p) {
   if (!p) return;
   int cur = 0;
@@ -204,6 +225,7 @@ void free_plan(cme_plan *p) {
   for (auto &c : p->classes) {
     if (c.d_order) (void)hipFree(c.d_order);
     if (c.d_tw) (void)hipFree(c.d_tw);
+    if (c.d_work) (void)hipFree(c.d_work);
     if (c.done) (void)hipEventDestroy(c.done);
     if (c.side) (void)hipStreamDestroy(c.side);
   }
@@ -234,6 +256,7 @@ cme::RunArgs run_args(const cme_plan *p, const SizeClass &c, void *A, int64_t st
   a.total = p->total;
   a.flags = p->d_flags;
   a.stages = stages;
+  a.work = c.d_work;
   return a;
 }
 
@@ -281,6 +304,7 @@ int autotune(cme_plan *p) {
     for (const Variant *v : candidates(p->precision, c.n, p->integrator + 16 * p->fwm))
       if (v != c.var) order.push_back(v);
     for (const Variant *v : order) {
+      if ((rc = ensure_work(p, c, v)) != CME_OK) break;
       SizeClass tmp = c;
       tmp.var = v;
       const cme::RunArgs a = run_args(p, tmp, state, 0, steps, 0, nullptr, nullptr);
@@ -313,7 +337,7 @@ int validate_instances(int32_t batch, const cme_instance *inst, int64_t *total) 
   int64_t tot = 0;
   for (int32_t b = 0; b < batch; ++b) {
     const cme_instance &x = inst[b];
-    if (!is_pow2(x.n_modes) || x.n_modes < 16 || x.n_modes > 8192) return CME_EINVAL;
+    if (!is_pow2(x.n_modes) || x.n_modes < 16 || x.n_modes > 65536) return CME_EINVAL;
     if (x.reserved != 0 || x.mode_offset < 0) return CME_EINVAL;
     const double vals[] = {x.kappa_ext, x.g0, x.a_in_re, x.a_in_im, x.sigma0, x.sigma1, x.tau_ramp};
     for (double v : vals)
@@ -367,6 +391,11 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   int64_t total = 0;
   int rc = validate_instances(batch, inst, &total);
   if (rc != CME_OK) return rc;
+  // transforms longer than 8192 points run only on the staged FP64 RK4 kernels
+  for (int32_t b = 0; b < batch; ++b)
+    if ((fwm == CME_FWM_PADDED ? 2 : 1) * inst[b].n_modes > 8192 &&
+        (precision != CME_F64 || integrator != CME_RK4 || fwm != CME_FWM_CYCLIC))
+      return CME_EUNSUPPORTED;
 
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return CME_ENODEVICE;
@@ -479,6 +508,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
                   hipMemcpyHostToDevice) != hipSuccess)
       rc = CME_EHIP;
     if (rc == CME_OK) rc = upload_twiddles(c.n, precision, &c.d_tw);
+    if (rc == CME_OK) rc = ensure_work(p, c, c.var);
     if (rc == CME_OK && !p->classes.empty() &&
         (hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking) != hipSuccess ||
          hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess))
@@ -521,8 +551,22 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
   if (ckpt && ckpt_every == 0) return CME_EINVAL;
   if (p->precision != CME_F64 || p->integrator != CME_RK4 || p->fwm != CME_FWM_CYCLIC)
     return CME_EUNSUPPORTED;
-  for (auto &c : p->classes)
-    if (!c.var->adj) return CME_EUNSUPPORTED;
+  // A class whose forward kernel has no reverse sweep (the staged kernels)
+  // recomputes and reverses with a variant of its size that has one; the
+  // forward kernels are restored on return.
+  std::vector<const Variant *> fwd_vars;
+  for (auto &c : p->classes) {
+    fwd_vars.push_back(c.var);
+    if (!adjoint_variant(p, c)) return CME_EUNSUPPORTED;
+  }
+  struct Restore {
+    cme_plan *p;
+    const std::vector<const Variant *> &v;
+    ~Restore() {
+      for (size_t i = 0; i < p->classes.size(); ++i) p->classes[i].var = v[i];
+    }
+  } restore{p, fwd_vars};
+  for (auto &c : p->classes) c.var = adjoint_variant(p, c);
   const size_t vec = p->elem * (size_t)p->total;
   if (n_steps == 0) {
     if (gA_0) HIP_TRY(hipMemcpyAsync(gA_0, gA_T, vec, hipMemcpyDefault, p->stream));
@@ -614,6 +658,8 @@ int cme_plan_select(cme_plan *p, int32_t n_modes, int32_t kernel_id) {
         v[kernel_id].precision != p->precision ||
         !integrates(v[kernel_id], p->integrator + 16 * p->fwm))
       return CME_EUNSUPPORTED;
+    const int rc = ensure_work(p, c, &v[kernel_id]);
+    if (rc != CME_OK) return rc;
     c.var = &v[kernel_id];
     return CME_OK;
   }

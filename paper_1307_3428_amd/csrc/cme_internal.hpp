@@ -38,6 +38,8 @@ struct RunArgs {
   int32_t *flags;          // [batch] non-finite flags
   void *stages;            // adjoint recompute: per step and stage, the stage input u_s
                            // and its inverse transform a_s, [K][4][2][total], or null
+  void *work;              // class workspace of variants with work > 0: `work` complex
+                           // values per mode for each instance of the class, in class order
 };
 
 // Arguments of one reverse (adjoint) launch over one segment of one class.
@@ -89,12 +91,15 @@ struct Variant {
                    // (cme_wave.hpp), 2: four rounds of two interleaved transforms
                    // per RK4 step (cme_duo.hip), 3: two-level kernel sized for two
                    // waves per SIMD (cme_lean.hip), 4: split-step map (cme_split.hip),
-                   // 5: RK4 with the padded (alias-free truncated) sum (cme_wave.hip)
+                   // 5: RK4 with the padded (alias-free truncated) sum (cme_wave.hip),
+                   // 6: RK4 with four-step transforms staged through global memory
+                   // (cme_staged.hip; `v` holds the row length N1)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
   FwdLaunch fwd;
   AdjLaunch adj;   // null if no adjoint kernel for this variant (FP32)
+  int work = 0;    // complex values of class workspace per mode (RunArgs::work)
 };
 
 const Variant *variants_team(int *count);  // cme_kernels.hip
@@ -104,6 +109,7 @@ const Variant *variants_wave_f32(int *count);  // cme_wave_f32.hip
 const Variant *variants_lean(int *count);  // cme_lean.hip
 const Variant *variants_duo(int *count);   // cme_duo.hip
 const Variant *variants_split(int *count); // cme_split.hip
+const Variant *variants_staged(int *count);  // cme_staged.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 }  // namespace cme

@@ -1,0 +1,258 @@
+// cme_staged.hip -- RK4 for mode counts whose transform does not fit one
+// workgroup (FP64 N >= 8192): four-step transforms whose transpose goes
+// through global memory (L2 / MALL / HBM) instead of LDS.
+//
+// N = N1 N2; mode index m = m1 + N1 m2 (m1 < N1, m2 < N2); transformed index
+// j = j2 + N2 j1.  With w_L = e^{2 pi i / L} and w = w_N, the inverse
+// transform of Eq. (4) factors as
+//   a_{j2 + N2 j1} = sum_m1 w_N1^{j1 m1} [ w^{j2 m1} sum_m2 u_{m1 + N1 m2} w_N2^{j2 m2} ]
+// and the forward transform of b = |a|^2 a as its mirror image
+//   N K_{m1 + N1 m2} = sum_j2 w_N2^{-j2 m2} [ w^{-j2 m1} sum_j1 b_{j2 + N2 j1} w_N1^{-j1 m1} ].
+// Both bracketed half-transforms are kept in one scratch array S[j2][m1] per
+// instance, and a step of the RK4 solver alternates two kernels:
+//   column kernel (a team of N2/E threads per m1): finish the forward
+//     transform (outer sum over j2) -> N K for the team's N2 modes; form the
+//     stage derivative k_s = L_s u_s + i (g0/N) N K + [m = N/2] pump, the RK4
+//     combination, the next stage input, and start its inverse transform
+//     (inner sum over m2, times w^{j2 m1}) into S;
+//   row kernel (a team of N1/E threads per j2): finish the inverse transform
+//     (outer sum over m1), cube pointwise, start the forward transform (inner
+//     sum over j1, times w^{-j2 m1}) into S.
+// A step is 4 x (row, column) launches; a run starts with one column launch
+// that only starts the inverse transform of the state.  The RK4 vectors
+// (accumulated derivative, stage input) live in a plan-owned workspace next to
+// S; the state is read and written in the caller's array.  Every launch moves
+// each of these arrays once, so the path is bound by memory traffic.
+//
+// Each team transforms its column or row with the radix-E Stockham passes of
+// cme_fft.hpp in registers, exchanging through a private LDS buffer inside
+// one wavefront (no workgroup barrier).
+#include "cme_fft.hpp"
+#include "cme_internal.hpp"
+
+namespace cme {
+
+namespace {
+
+struct StagedArgs {
+  const DevInst *inst;
+  const int32_t *order;
+  int32_t count;
+  int32_t tail;            // column kernel, last stage of the run: no next transform
+  cx<double> *A;           // caller's packed state
+  const double *kappa;
+  const double *omega;
+  const cx<double> *tab;   // exp(-2 pi i k / N), k < N
+  cx<double> *work;        // per class slot: S, acc, u (3 N each)
+  double h;
+  double t0;               // time at the start of the step
+  cx<double> *ckpt;        // checkpoint row for this step (packed like A) or null
+  int32_t *flags;
+};
+
+constexpr int kPS = 3;  // one LDS pad element every 8
+
+// RK4 stage nodes
+__device__ __forceinline__ constexpr double stage_c(int s) { return s == 0 ? 0.0 : (s == 3 ? 1.0 : 0.5); }
+
+template <int N, int N1, int E, int WPB> struct ColShape {
+  static constexpr int N2 = N / N1;
+  static constexpr int T = N2 / E;       // threads per column
+  static constexpr int CW = 64 / T;      // columns per wavefront
+  static constexpr int C = CW * WPB;     // columns per workgroup
+  static constexpr int NB = N1 / C;      // workgroups per instance
+  static constexpr int LB = LdsLen<N2, kPS>::value + 1;
+  static constexpr int LDS_BYTES = WPB * CW * LB * 16;
+  static_assert(T >= 1 && T <= 64 && N1 % C == 0, "column shape");
+};
+
+template <int N, int N1, int E, int WPB> struct RowShape {
+  static constexpr int N2 = N / N1;
+  static constexpr int T = N1 / E;       // threads per row
+  static constexpr int RW = 64 / T;      // rows per wavefront
+  static constexpr int R = RW * WPB;     // rows per workgroup
+  static constexpr int NB = N2 / R;      // workgroups per instance
+  static constexpr int LB = LdsLen<N1, kPS>::value + 1;
+  static constexpr int LDS_BYTES = WPB * RW * LB * 16;
+  static_assert(T >= 1 && T <= 64 && N2 % R == 0, "row shape");
+};
+
+// STAGE < 0: start the inverse transform of the state (first launch of a run);
+// STAGE = s in 0..3: RK4 stage s + 1 as described above.
+template <int N, int N1, int E, int WPB, int STAGE>
+__global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
+  using SH = ColShape<N, N1, E, WPB>;
+  constexpr int N2 = SH::N2, T = SH::T;
+  __shared__ cx<double> lds[WPB * SH::CW * SH::LB];
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x / SH::NB, cb = (int)blockIdx.x % SH::NB;
+  const int cl = lane % SH::CW, t = lane / SH::CW;
+  const int m1 = cb * SH::C + wv * SH::CW + cl;
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  cx<double> *A = a.A + d.a_offset;
+  cx<double> *S = a.work + (int64_t)slot * 3 * N;
+  cx<double> *ACC = S + N, *U = S + 2 * N;
+  cx<double> *buf = lds + (wv * SH::CW + cl) * SH::LB;
+
+  cx<double> tw[FftPlan<N2, E>::NTW];
+  load_twiddles<N2, E, N1>(tw, a.tab, t);
+  cx<double> v[E];
+
+  if constexpr (STAGE < 0) {
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      v[m] = A[m1 + N1 * (t + m * T)];
+    });
+  } else {
+    // outer sum of the forward transform: v[m] = N K at mode m1 + N1 (t + m T)
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      v[m] = S[(t + m * T) * N1 + m1];
+    });
+    fft_team<N2, E, -1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+    const double h = a.h;
+    const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
+    const double *kap = a.kappa + d.offset, *omg = a.omega + d.offset;
+    bool bad = false;
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const int i = m1 + N1 * (t + m * T);
+      const cx<double> y = A[i];
+      const cx<double> u = STAGE == 0 ? y : U[i];
+      const double lr = -0.5 * kap[i], li = omg[i] - sig;
+      // k = L u + i (g0/N) N K
+      cx<double> k = {lr * u.re - li * u.im - d.g0n * v[m].im, lr * u.im + li * u.re + d.g0n * v[m].re};
+      if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
+      cx<double> nxt;
+      if constexpr (STAGE == 0) {
+        ACC[i] = k;
+        nxt = {y.re + 0.5 * h * k.re, y.im + 0.5 * h * k.im};
+        U[i] = nxt;
+      } else if constexpr (STAGE < 3) {
+        const cx<double> acc = ACC[i];
+        ACC[i] = {acc.re + 2.0 * k.re, acc.im + 2.0 * k.im};
+        const double c = STAGE == 1 ? 0.5 * h : h;
+        nxt = {y.re + c * k.re, y.im + c * k.im};
+        U[i] = nxt;
+      } else {
+        const cx<double> acc = ACC[i];
+        const double c = h / 6.0;
+        nxt = {y.re + c * (acc.re + k.re), y.im + c * (acc.im + k.im)};
+        A[i] = nxt;
+        if (a.ckpt) a.ckpt[d.a_offset + i] = nxt;
+        bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
+      }
+      v[m] = nxt;
+    });
+    if constexpr (STAGE == 3) {
+      if (bad) atomicOr(&a.flags[id], 1);
+      if (a.tail) return;
+    }
+  }
+  // inner sum of the inverse transform over m2, times w^{+j2 m1}
+  fft_team<N2, E, +1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int j2 = t + m * T;
+    S[j2 * N1 + m1] = cmulc(v[m], a.tab[(j2 * m1) & (N - 1)]);
+  });
+}
+
+template <int N, int N1, int E, int WPB>
+__global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgs a) {
+  using SH = RowShape<N, N1, E, WPB>;
+  constexpr int T = SH::T;
+  __shared__ cx<double> lds[WPB * SH::RW * SH::LB];
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x / SH::NB, rb = (int)blockIdx.x % SH::NB;
+  const int team = lane / T, t = lane % T;
+  const int j2 = rb * SH::R + wv * SH::RW + team;
+  cx<double> *S = a.work + (int64_t)slot * 3 * N + (int64_t)j2 * N1;
+  cx<double> *buf = lds + (wv * SH::RW + team) * SH::LB;
+
+  cx<double> tw[FftPlan<N1, E>::NTW];
+  load_twiddles<N1, E, N / N1>(tw, a.tab, t);
+  cx<double> v[E];
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    v[m] = S[t + m * T];
+  });
+  // outer sum of the inverse transform over m1: a_{j2 + N2 j1}, j1 = t + m T
+  fft_team<N1, E, +1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const double p = v[m].re * v[m].re + v[m].im * v[m].im;
+    v[m] = {p * v[m].re, p * v[m].im};
+  });
+  // inner sum of the forward transform over j1, times w^{-j2 m1}
+  fft_team<N1, E, -1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int m1 = t + m * T;
+    S[m1] = cmul(v[m], a.tab[(j2 * m1) & (N - 1)]);
+  });
+}
+
+template <int N, int N1, int E, int WPB>
+hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
+  using CS = ColShape<N, N1, E, WPB>;
+  using RS = RowShape<N, N1, E, WPB>;
+  if (r.stages != nullptr || r.work == nullptr) return hipErrorInvalidValue;
+  if (r.count <= 0 || r.n_steps <= 0) return hipSuccess;
+  StagedArgs a{};
+  a.inst = r.inst;
+  a.order = r.order;
+  a.count = r.count;
+  a.A = reinterpret_cast<cx<double> *>(r.A);
+  a.kappa = r.kappa;
+  a.omega = r.omega;
+  a.tab = reinterpret_cast<const cx<double> *>(r.twiddle);
+  a.work = reinterpret_cast<cx<double> *>(r.work);
+  a.h = r.h;
+  a.flags = r.flags;
+  const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
+  cx<double> *ck = reinterpret_cast<cx<double> *>(r.ckpt);
+  a.t0 = (double)r.step0 * r.h;
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1>), cgrid, blk, 0, st, a);
+  int64_t slot = 0;
+  for (int64_t n = 0; n < r.n_steps; ++n) {
+    a.t0 = (double)(r.step0 + n) * r.h;
+    a.ckpt = nullptr;
+    if (ck && r.ckpt_every > 0 && (n + 1) % r.ckpt_every == 0) a.ckpt = ck + (slot++) * r.total;
+    a.tail = n + 1 == r.n_steps;
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3>), cgrid, blk, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N, int N1, int E, int WPB> constexpr Variant staged_variant() {
+  using CS = ColShape<N, N1, E, WPB>;
+  using RS = RowShape<N, N1, E, WPB>;
+  return Variant{0, N, E, N1, kPS, 0, 6, 1, 64 * WPB,
+                 CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES,
+                 &launch_staged<N, N1, E, WPB>, nullptr, 3};
+}
+
+// (N, N1, E, waves per workgroup); the field `v` of a variant holds N1
+const Variant kStagedVariants[] = {
+    staged_variant<8192, 128, 8, 4>(),  staged_variant<8192, 64, 8, 4>(),
+    staged_variant<16384, 128, 8, 4>(), staged_variant<32768, 256, 8, 4>(),
+    staged_variant<65536, 256, 8, 4>(),
+};
+
+}  // namespace
+
+const Variant *variants_staged(int *count) {
+  *count = (int)(sizeof(kStagedVariants) / sizeof(kStagedVariants[0]));
+  return kStagedVariants;
+}
+
+}  // namespace cme

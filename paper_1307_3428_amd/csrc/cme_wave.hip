@@ -13,7 +13,7 @@ static const Variant kWaveVariants[] = {
     wave_variant<double, 512, 4, 1, 2>(),     wave_variant<double, 1024, 8, 1, 3>(),
     wave_variant<double, 1024, 4, 1, 2>(),    wave_variant<double, 2048, 8, 1, 3>(),
     wave_variant<double, 2048, 8, 1, 3, 1>(), wave_variant<double, 4096, 8, 1, 3>(),
-    wave_variant<double, 8192, 16, 2, 3, 1>(), wave_variant<double, 8192, 16, 2, 3>(),
+    wave_variant<double, 8192, 16, 2, 3>(),   wave_variant<double, 8192, 16, 2, 3, 1>(),
 };
 
 // Alias-free truncated sum (CME_FWM_PADDED): instances of N/2 = 128 ... 4096

@@ -45,7 +45,7 @@ def test_strerror_and_version():
 
 def test_kernel_table_covers_every_size():
     seen = set()
-    for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192):
+    for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536):
         ids = C.cme_list_kernels(C.CME_F64, n)
         assert ids, n
         for k in ids:
@@ -53,12 +53,23 @@ def test_kernel_table_covers_every_size():
             assert info["n_modes"] == n and info["precision"] == C.CME_F64
             e = info["elems_per_thread"]
             assert e & (e - 1) == 0 and 2 <= e <= n
-            assert info["threads"] == info["instances_per_group"] * (n // e)
             assert info["threads"] <= 1024 and info["lds_bytes"] <= 160 * 1024
-            if info["kind"] >= 1:     # two-level kernels: whole wavefronts per instance
+            if info["kind"] == 6:
+                # staged: rows of N1 and columns of N / N1 points, each a
+                # team of whole lanes inside one wavefront
+                n1 = info["sub_transforms"]
+                assert n % n1 == 0 and 64 % (n1 // e) == 0 and 64 % (n // n1 // e) == 0
+                assert info["threads"] % 64 == 0
+            else:
+                assert info["threads"] == info["instances_per_group"] * (n // e)
+            if info["kind"] in (1, 2, 3, 4, 5):  # two-level kernels: whole wavefronts per instance
                 assert (n // e) % 64 == 0
             seen.add(k)
+        # above 8192 only the staged kernels
+        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] == 6 for k in ids)
+        assert n <= 8192 or C.cme_list_kernels(C.CME_F32, n) == []
     assert C.cme_list_kernels(C.CME_F64, 100) == []
+    assert C.cme_list_kernels(C.CME_F64, 131072) == []
     with pytest.raises(C.CmeError):
         C.cme_kernel_info(10 ** 6)
 
@@ -86,7 +97,8 @@ def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan
                                   "n_too_small", "neg_h", "nan_h", "bad_precision",
                                   "reserved", "neg_offset", "overlap", "bad_flags",
                                   "nan_sigma", "neg_kext", "bad_integrator", "split_fp32",
-                                  "bad_fwm", "padded_split"])
+                                  "bad_fwm", "padded_split", "large_fp32", "large_split",
+                                  "large_padded"])
 def test_init_rejects_invalid_arguments_without_a_device(case):
     kappa = np.ones(256)
     omega = np.zeros(256)
@@ -102,7 +114,7 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
     elif case == "bad_n":
         inst = _inst(n=48)
     elif case == "n_too_big":
-        inst = _inst(n=16384)
+        inst = _inst(n=131072)
     elif case == "n_too_small":
         inst = _inst(n=8)
     elif case == "neg_h":
@@ -132,6 +144,13 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
     elif case == "padded_split":
         kw["fwm"] = C.CME_FWM_PADDED
         kw["integrator"] = C.CME_SPLIT_STEP
+        expect = C.CME_EUNSUPPORTED
+    elif case in ("large_fp32", "large_split", "large_padded"):
+        # above 8192 transform points only FP64 RK4 with the cyclic sum
+        inst = _inst(n=16384 if case != "large_padded" else 8192)
+        kw.update({"large_fp32": {"precision": C.CME_F32},
+                   "large_split": {"integrator": C.CME_SPLIT_STEP},
+                   "large_padded": {"fwm": C.CME_FWM_PADDED}}[case])
         expect = C.CME_EUNSUPPORTED
     elif case == "split_fp32":
         kw["integrator"] = C.CME_SPLIT_STEP
