@@ -101,6 +101,9 @@ def main() -> int:
     ap.add_argument("--kernel", type=int, default=-1, help="force a kernel variant id")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--staged-case", type=int, default=0, metavar="N",
+                    help="only run the staged kernel on the staged leg's batch of size N "
+                         "(8192, 16384 or 65536) for --rk-steps steps (profiling) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -129,6 +132,11 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 8}))
+        return 0
+
+    if args.staged_case:
+        print(json.dumps(staged_leg(C, W, torch, only=args.staged_case,
+                                    steps=args.rk_steps or 20)))
         return 0
 
     rk_steps = args.rk_steps or 50000
@@ -336,26 +344,30 @@ def uneven_leg(C, W, torch, steps=20000):
 STAGED_BYTES_PER_MODE_STEP = (16 * 5 + 16) + 2 * (16 * 7 + 16) + (16 * 6 + 16) + 4 * 32
 
 
-def staged_leg(C, W, torch):
+def staged_leg(C, W, torch, only=0, steps=None):
     """The staged path (four-step transforms through global memory): FP64,
     N = 8192 against the LDS-resident kernel, and N = 16384 / 65536, where it
     is the only kernel; about 10^6 modes per plan (seeded random instances,
-    RK4 h = 2e-4)."""
+    RK4 h = 2e-4).  only = N: just the first staged kernel of that size."""
     out = {"bytes_per_mode_step": STAGED_BYTES_PER_MODE_STEP, "peak_GBps": 8000.0, "cases": []}
-    for n, b, steps in ((8192, 128, 200), (16384, 64, 200), (65536, 16, 100)):
+    for n, b, default_steps in ((8192, 128, 200), (16384, 64, 200), (65536, 16, 100)):
+        if only and n != only:
+            continue
+        nsteps = steps or default_steps
         p = W.pack(W.random_batch(43, [n] * b, noise=1e-3))
-        ids = [k for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] in (1, 6)]
+        ids = [k for k in C.cme_list_kernels(C.CME_F64, n)
+               if C.cme_kernel_info(k)["kind"] in ((6,) if only else (1, 6))][:1 if only else None]
         for kid in ids:
             with C.Plan(p, 2e-4) as plan:
                 plan.select(n, kid)
                 A = plan.state(p.a0)
                 plan.run(A, 10)
                 torch.cuda.synchronize()
-                s = timed_run(plan, A, steps, torch)
+                s = timed_run(plan, A, nsteps, torch)
                 name = plan.kernel(n)["name"]
-            rate = p.total * steps / s
-            case = {"workload": f"{b} x N={n}, {steps} RK4 steps", "kernel": name,
-                    "mode_steps_per_s": rate, "us_per_step": 1e6 * s / steps}
+            rate = p.total * nsteps / s
+            case = {"workload": f"{b} x N={n}, {nsteps} RK4 steps", "kernel": name,
+                    "mode_steps_per_s": rate, "us_per_step": 1e6 * s / nsteps}
             if name.startswith("rk4_staged"):
                 gbps = rate * STAGED_BYTES_PER_MODE_STEP / 1e9
                 case.update({"algorithmic_GBps": gbps, "frac_hbm_peak": gbps / 8000.0})
