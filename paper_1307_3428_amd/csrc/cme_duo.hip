@@ -7,16 +7,17 @@
 // K'_s = DFT(b_s) (so the four-wave-mixing term is (g0/N) K'_s):
 //   k_s        = W_s + i (g0/N) K'_s,           b_s = |a_s|^2 a_s,
 //   a_s        = IDFT(u_s),  IDFT(k_s) = IDFT(W_s) + i g0 b_s  (IDFT DFT = N),
-//   a_{s+1}    = IDFT(y) + c_{s+1} h (IDFT(W_s) + i g0 b_s).
-// Hence, with Y = IDFT(y) and Z_s = IDFT(W_s):
-//   R0: Y, Z_1                 (inverse transforms of y and W_1 = L_1 y + p)
-//       a_2 = Y + h/2 (Z_1 + i g0 b_1)
-//   R1: K'_1, K'_2             (forward transforms of b_1 = |Y|^2 Y and b_2)
+//   a_{s+1}    = IDFT(y + c_{s+1} h W_s) + c_{s+1} h i g0 b_s.
+// Hence:
+//   R0: a_1 = IDFT(y), V_1 = IDFT(y + h/2 W_1)      (W_1 = L_1 y + p)
+//       a_2 = V_1 + h/2 i g0 b_1
+//   R1: K'_1, K'_2             (forward transforms of b_1 and b_2)
 //       k_1, u_2, W_2, k_2, u_3, W_3
-//   R2: Z_2, Z_3               (inverse transforms of W_2 and W_3)
-//       a_3 = Y + h/2 (Z_2 + i g0 b_2),  a_4 = Y + h (Z_3 + i g0 b_3)
+//   R2: a_3 = IDFT(u_3), V_3 = IDFT(y + h W_3)
+//       a_4 = V_3 + h i g0 b_3
 //   R3: K'_3, K'_4             (forward transforms of b_3 and b_4)
 //       k_3, u_4, W_4, k_4;  y += h/6 (k_1 + 2 k_2 + 2 k_3 + k_4).
+// Only y, the RK4 accumulator and W_3 live across rounds.
 // Eight transforms in four rounds; the two of a round have the same
 // direction and structure, so their passes are interleaved: while one
 // transform's LDS exchange is in flight the wave computes the other's
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
-  cx<Real> y[E], acc[E], yt[E], keep[E], va[E], vb[E];
+  cx<Real> y[E], acc[E], w3[E], va[E], vb[E];
   Real lr[E];
   double om[E];
   sfor<0, E>([&](auto mi) {
@@ -433,25 +434,24 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
     const double s1 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0);
     const double s2 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + 0.5 * h);
     const double s4 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + h);
-    // ---- R0: Y = IDFT(y), Z_1 = IDFT(W_1)
+    // ---- R0: a_1 = IDFT(y), IDFT(y + h/2 W_1)
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       rec_u(n, 0, mi, y[m]);
       va[m] = y[m];
-      vb[m] = lin(y[m], mi, s1);
+      const cx<Real> w1 = lin(y[m], mi, s1);
+      vb[m] = {y[m].re + hh * w1.re, y[m].im + hh * w1.im};
     });
     lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      yt[m] = va[m];
       rec_a(n, 0, mi, va[m]);
       const cx<Real> b1 = cube(va[m]);
-      const cx<Real> a2 = {va[m].re + hh * (vb[m].re - gt * b1.im),
-                           va[m].im + hh * (vb[m].im + gt * b1.re)};
+      // a_2 = IDFT(y + h/2 (W_1 + i (g0/N) DFT b_1)) = IDFT(y + h/2 W_1) + h/2 i g0 b_1
+      const cx<Real> a2 = {vb[m].re - hh * gt * b1.im, vb[m].im + hh * gt * b1.re};
       rec_a(n, 1, mi, a2);
       va[m] = b1;
       vb[m] = cube(a2);
-      keep[m] = vb[m];  // b_2, for a_3
     });
     // ---- R1: K'_1, K'_2
     lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
@@ -466,22 +466,18 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       acc[m] = {k1.re + (Real)2 * k2.re, k1.im + (Real)2 * k2.im};
       const cx<Real> u3 = {y[m].re + hh * k2.re, y[m].im + hh * k2.im};
       rec_u(n, 2, mi, u3);
-      va[m] = w2;
-      vb[m] = lin(u3, mi, s2);
+      w3[m] = lin(u3, mi, s2);
+      va[m] = u3;
+      vb[m] = {y[m].re + hf * w3[m].re, y[m].im + hf * w3[m].im};
     });
-    // ---- R2: Z_2, Z_3
-    cx<Real> w3[E];
-    sfor<0, E>([&](auto mi) { w3[decltype(mi)::value] = vb[decltype(mi)::value]; });
+    // ---- R2: a_3 = IDFT(u_3), IDFT(y + h W_3)
     lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      const cx<Real> b2 = keep[m];
-      const cx<Real> a3 = {yt[m].re + hh * (va[m].re - gt * b2.im),
-                           yt[m].im + hh * (va[m].im + gt * b2.re)};
-      rec_a(n, 2, mi, a3);
-      const cx<Real> b3 = cube(a3);
-      const cx<Real> a4 = {yt[m].re + hf * (vb[m].re - gt * b3.im),
-                           yt[m].im + hf * (vb[m].im + gt * b3.re)};
+      rec_a(n, 2, mi, va[m]);
+      const cx<Real> b3 = cube(va[m]);
+      // a_4 = IDFT(y + h (W_3 + i (g0/N) DFT b_3)) = IDFT(y + h W_3) + h i g0 b_3
+      const cx<Real> a4 = {vb[m].re - hf * gt * b3.im, vb[m].im + hf * gt * b3.re};
       rec_a(n, 3, mi, a4);
       va[m] = b3;
       vb[m] = cube(a4);
@@ -746,6 +742,7 @@ template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant
 // instance) is left to the lean kernel.
 static const Variant kDuoVariants[] = {
     duo_variant<double, 1024, 8, 3, 4, 1>(),
+    duo_variant<double, 2048, 8, 3, 5, 1>(),
     duo_variant<double, 2048, 8, 3, 4, 1>(),
     duo_variant<double, 2048, 8, 3, 4, 0>(),
 };
