@@ -18,7 +18,8 @@ Also reported on the same JSON line:
                 sample of the same workload on this host's cores;
   adjoint       forward-with-checkpoints and adjoint times for the N = 2048,
                 5000-step gradient workload and their ratio;
-  single        a single N = 1024 instance (soliton ramp) on one workgroup;
+  single        single instances on one workgroup (plain N = 128, soliton
+                ramp N = 1024), also as a fraction of one CU's FP64 peak;
   fp32          the same sweep in FP32 (FP64 time bookkeeping);
   uneven        the uneven-octave batch (512 instances, N in {1024, ..., 8192},
                 h = 2e-4, 2e4 steps) in FP64 and FP32, classic RK4 on the
@@ -410,24 +411,34 @@ def fig1_leg(C, W, torch):
 
 
 def single_leg(C, W, torch):
-    """One N=1024 instance on one workgroup: soliton ramp workload, 20000 steps."""
+    """Single instances, each on one workgroup (one CU): the plain N=128
+    workload and the N=1024 soliton ramp, 20000 RK4 steps each.  Reported
+    against one CU's FP64 vector peak (128 flop/clk at 2.4 GHz) as well as
+    the device's: one instance cannot use more than one CU."""
     steps = 20000
-    wl = W.soliton_ramp_n1024(n_steps=steps)
-    p = W.pack(wl.instances)
-    with C.Plan(p, wl.h, flags=C.CME_INIT_AUTOTUNE) as plan:
-        A = plan.state(p.a0)
-        plan.run(A, 1000)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        plan.run(A, steps, step0=1000)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        k = plan.kernel(1024)
-    return {"workload": "soliton_ramp_n1024 (one instance), 20000 RK4 steps",
-            "mode_steps_per_s": 1024 * steps / (ms / 1e3), "us_per_rk4_step": ms * 1e3 / steps,
-            "kernel": k}
+    cu_peak = 128 * 2.4e9
+    out = {}
+    for name, wl in (("plain_n128", W.plain_n128(n_steps=steps)),
+                     ("soliton_ramp_n1024", W.soliton_ramp_n1024(n_steps=steps))):
+        p = W.pack(wl.instances)
+        n = int(p.n_modes[0])
+        with C.Plan(p, wl.h, flags=C.CME_INIT_AUTOTUNE) as plan:
+            A = plan.state(p.a0)
+            plan.run(A, 1000)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            plan.run(A, steps, step0=1000)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            k = plan.kernel(n)
+        flops = counted_flops_per_step(n) * steps / (ms / 1e3)
+        out[name] = {"workload": f"{name} (one instance), {steps} RK4 steps",
+                     "mode_steps_per_s": n * steps / (ms / 1e3), "us_per_rk4_step": ms * 1e3 / steps,
+                     "counted_GFLOPs": flops / 1e9, "frac_one_cu_fp64_peak": flops / cu_peak,
+                     "frac_device_fp64_peak": flops / 78.6e12, "kernel": k["name"]}
+    return out
 
 
 if __name__ == "__main__":
