@@ -303,8 +303,11 @@ def fp32_leg(C, W, torch, rk_steps):
         torch.cuda.synchronize()
         s = timed_run(plan, A, rk_steps, torch)
         k = plan.kernel(2048)
+    rate = p.total * rk_steps / s
     return {"workload": f"sweep_n2048 in FP32, {rk_steps} RK4 steps",
-            "mode_steps_per_s": p.total * rk_steps / s, "kernel": k["name"]}
+            "mode_steps_per_s": rate, "kernel": k["name"],
+            "counted_TFLOPs": rate * counted_flops_per_step(2048) / 2048 / 1e12,
+            "frac_fp32_vector_peak": rate * counted_flops_per_step(2048) / 2048 / 157.3e12}
 
 
 def rk4_stable(inst, h):

@@ -38,6 +38,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_team(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_duo_f32(&n);
+    v.insert(v.end(), a, a + n);
     a = variants_wave_f32(&n);
     v.insert(v.end(), a, a + n);
     a = variants_staged(&n);

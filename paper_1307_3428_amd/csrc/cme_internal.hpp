@@ -108,6 +108,7 @@ const Variant *variants_pad(int *count);       // cme_wave.hip (padded sum)
 const Variant *variants_wave_f32(int *count);  // cme_wave_f32.hip
 const Variant *variants_lean(int *count);  // cme_lean.hip
 const Variant *variants_duo(int *count);   // cme_duo.hip
+const Variant *variants_duo_f32(int *count);  // cme_duo.hip (FP32)
 const Variant *variants_split(int *count); // cme_split.hip
 const Variant *variants_staged(int *count);  // cme_staged.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
