@@ -525,10 +525,12 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
 // and a step takes four rounds of two transforms:
 //   A: Ybar, P_4             -> z_4, q_4, z_3, q_3
 //   B: DFT q_4, q_3          -> ubar_4, kbar_3, ubar_3, kbar_2
-//   C: IDFT(ubar_3), P_2     -> z_2, q_2, z_1, q_1
+//   C: IDFT(kbar_2), IDFT(h/6 ybar' + h/2 conj(L_2) kbar_2)
+//                            -> z_2, q_2, z_1, q_1
 //   D: DFT q_2, q_1          -> ubar_2, kbar_1, ubar_1;  ybar = ybar' + sum ubar_s
-// (round C transforms ubar_3 itself, which is known by then: IDFT(ubar_3) =
-// P_3 + N q_3).
+// (round C transforms the combinations themselves, known after round B:
+// IDFT(kbar_2) = h/3 Ybar + h/2 IDFT(ubar_3), so Ybar need not be kept from
+// round A to round C).
 // Parameter cotangents per stage: gbar_omega += Re(conj(kbar) i u),
 // gbar_kappa -= Re(conj(kbar) u) / 2, gbar_Ain += sqrt(kappa_ext) kbar at
 // mu = 0.  The stage records (u_s in mode order, a_s in the time-domain
@@ -554,7 +556,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
   std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
-  cx<Real> yb1[E], yb[E], ybt[E], k2[E], va[E], vb[E], ra[E], rb[E];
+  cx<Real> yb1[E], yb[E], k2[E], va[E], vb[E], ra[E], rb[E];
   Real lr[E], gom[E], gka[E];
   double om[E];
   sfor<0, E>([&](auto mi) {
@@ -632,7 +634,6 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      ybt[m] = va[m];
       const cx<Real> q4 = kerr_t(mig(cx<Real>{hw1 * va[m].re, hw1 * va[m].im}), ra[m]);
       const cx<Real> x3 = {hw2 * va[m].re + hf * (vb[m].re + nn_r * q4.re),
                            hw2 * va[m].im + hf * (vb[m].im + nn_r * q4.im)};
@@ -655,19 +656,19 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       grads(mi, k3, rb[m]);
       yb[m] = {yb1[m].re + ub4.re + ub3.re, yb1[m].im + ub4.im + ub3.im};
       k2[m] = {hw2 * yb1[m].re + hh * ub3.re, hw2 * yb1[m].im + hh * ub3.im};
-      va[m] = ub3;
-      vb[m] = clin(k2[m], mi, s2);
+      const cx<Real> c2 = clin(k2[m], mi, s2);
+      va[m] = k2[m];
+      vb[m] = {hw1 * yb1[m].re + hh * c2.re, hw1 * yb1[m].im + hh * c2.im};
     });
-    // ---- C: IDFT(ubar_3) = P_3 + N q_3, P_2
+    // ---- C: IDFT(kbar_2) = h/3 Ybar + h/2 IDFT(ubar_3),
+    //         IDFT(h/6 ybar' + h/2 conj(L_2) kbar_2) = h/6 Ybar + h/2 P_2
     load_a(ra, nn, 1);
     load_a(rb, nn, 0);
     lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      const cx<Real> x2 = {hw2 * ybt[m].re + hh * va[m].re, hw2 * ybt[m].im + hh * va[m].im};
-      const cx<Real> q2 = kerr_t(mig(x2), ra[m]);
-      const cx<Real> x1 = {hw1 * ybt[m].re + hh * (vb[m].re + nn_r * q2.re),
-                           hw1 * ybt[m].im + hh * (vb[m].im + nn_r * q2.im)};
+      const cx<Real> q2 = kerr_t(mig(va[m]), ra[m]);
+      const cx<Real> x1 = {vb[m].re + hh * nn_r * q2.re, vb[m].im + hh * nn_r * q2.im};
       va[m] = q2;
       vb[m] = kerr_t(mig(x1), rb[m]);
     });
