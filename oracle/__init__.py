@@ -72,6 +72,8 @@ def load() -> ctypes.CDLL:
                                    ctypes.c_int, P, i64]),
         "orc_adjoint": (ctypes.c_int, [ctypes.c_int, P, P, P, dbl, i64, i64, P, P, P, P, P, P]),
         "orc_split_step_run": (ctypes.c_int, [ctypes.c_int, P, P, P, dbl, i64, i64, P]),
+        "orc_rk4ip_run": (ctypes.c_int, [ctypes.c_int, P, P, P, dbl, i64, i64, P]),
+        "orc_sigma_integral": (dbl, [P, dbl, dbl]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -189,3 +191,19 @@ def split_step_run(packed, h: float, n_steps: int, step0: int = 0, y0=None) -> n
                                    int(n_steps), _ptr(y))
     _check(rc, "split_step_run")
     return y
+
+
+def rk4ip_run(packed, h: float, n_steps: int, step0: int = 0, y0=None) -> np.ndarray:
+    """Interaction-picture RK4 over the packed batch (cyclic sum)."""
+    arr = _instances(packed)
+    y = _c128(packed.a0 if y0 is None else y0).copy()
+    kap, om = _f64(packed.kappa), _f64(packed.omega)
+    rc = load().orc_rk4ip_run(packed.batch, arr, _ptr(kap), _ptr(om), float(h), int(step0),
+                              int(n_steps), _ptr(y))
+    _check(rc, "rk4ip_run")
+    return y
+
+
+def sigma_integral(packed, b: int, t0: float, t1: float) -> float:
+    arr = _instances(packed)
+    return float(load().orc_sigma_integral(ctypes.byref(arr[b]), float(t0), float(t1)))

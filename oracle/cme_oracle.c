@@ -37,6 +37,9 @@
  *         C_d = sum_b conj(u_{b+d}) u_b,  S_s = sum_a u_a u_{s-a},
  *     which is the transpose, under Re<x, y> = Re sum conj(x) y, of
  *     du -> dK(u) = 2 K-terms linear in u + the term linear in conj(u).
+ *   - Interaction-picture RK4 (RK4IP): classic RK4 on the variable with the
+ *     exact linear propagator of each mode factored out, so the stiff
+ *     dispersion does not bound the step (see orc_rk4ip_run).
  *   - The frequency-domain split-step map (Sec. 2, the second method):
  *     Strang splitting with the linear part (loss, detuning, pump) solved
  *     exactly per mode and the Kerr part solved exactly on the transformed
@@ -471,6 +474,100 @@ int orc_split_step_run(int batch, const orc_instance *inst, const double *kappa,
       linear_exact(p, kappa + p->offset, omega + p->offset, t0 + 0.75 * h, 0.5 * h, yb);
     }
     free(a);
+  }
+  return status;
+}
+
+/* ---------------------------------------------------------------------------
+ * Interaction-picture fourth-order Runge-Kutta (RK4IP).  Split the right-hand
+ * side of Eq. (1) into the linear rate of each mode,
+ *     L_mu(t) = -kappa_mu/2 + i(omega'_mu - sigma(t)),
+ * and the rest, N(u) = i g0 K(u) + [mu == 0] sqrt(kappa_ext) A_in.  Over one
+ * step from t0, with tm = t0 + h/2, the variable B(t) = exp(-int_tm^t L) A(t)
+ * obeys dB/dt = exp(-int_tm^t L) N(exp(int_tm^t L) B), and classic RK4 on B,
+ * mapped back to A, reads (P1 = exp(int_t0^tm L), P2 = exp(int_tm^{t0+h} L),
+ * per mode; the integrals are exact because sigma is piecewise linear):
+ *     yI = P1 y,              k1 = P1 N(y),
+ *     k2 = N(yI + h/2 k1),    k3 = N(yI + h/2 k2),    k4 = N(P2 (yI + h k3)),
+ *     y' = P2 (yI + h/6 (k1 + 2 k2 + 2 k3)) + h/6 k4.
+ * The linear part, dispersion included, is integrated exactly, so the RK4
+ * stability bound on h max |L| does not apply.
+ * ------------------------------------------------------------------------- */
+
+/* integral of sigma(t) over [a, b], 0 <= a <= b */
+static double sigma_integral(const orc_instance *p, double a, double b) {
+  if (!(p->tau_ramp > 0.0)) return p->sigma0 * (b - a);
+  const double T = p->tau_ramp, slope = (p->sigma1 - p->sigma0) / T;
+  double ramp; /* integral of min(t, T) */
+  if (b <= T) ramp = 0.5 * (b - a) * (b + a);
+  else if (a >= T) ramp = T * (b - a);
+  else ramp = 0.5 * (T - a) * (T + a) + T * (b - T);
+  return p->sigma0 * (b - a) + slope * ramp;
+}
+
+static void nonlinear_part(const orc_instance *p, const cplx *u, cplx *f, rhs_work *w, int par) {
+  const int n = p->n;
+  fwm_cyclic(n, u, w->K, w->C, par);
+  for (int i = 0; i < n; ++i) f[i] = I * p->g0 * w->K[i];
+  f[n / 2] += sqrt(p->kappa_ext) * (p->ain_re + I * p->ain_im);
+}
+
+double orc_sigma_integral(const orc_instance *p, double a, double b) {
+  return sigma_integral(p, a, b);
+}
+
+int orc_rk4ip_run(int batch, const orc_instance *inst, const double *kappa, const double *omega,
+                  double h, int64_t step0, int64_t n_steps, cplx *y) {
+  if (!valid_batch(batch, inst) || !(h > 0.0) || n_steps < 0 || step0 < 0) return ORC_EINVAL;
+  int status = ORC_OK;
+  const int outer = batch >= orc_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) if (outer) num_threads(orc_max_threads())
+  for (int b = 0; b < batch; ++b) {
+    const orc_instance *p = &inst[b];
+    const int n = p->n;
+    const double *kap = kappa + p->offset, *om = omega + p->offset;
+    rhs_work rw;
+    rw.K = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    rw.C = (cplx *)malloc(sizeof(cplx) * (size_t)(2 * n));
+    cplx *P1 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *P2 = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *yi = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *u = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *k = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    cplx *acc = (cplx *)malloc(sizeof(cplx) * (size_t)n);
+    if (!rw.K || !rw.C || !P1 || !P2 || !yi || !u || !k || !acc) {
+      status = ORC_ENOMEM;
+    } else {
+      cplx *yb = y + p->offset;
+      for (int64_t s = 0; s < n_steps; ++s) {
+        const double t0 = (double)(step0 + s) * h, tm = t0 + 0.5 * h, t1 = t0 + h;
+        const double S1 = sigma_integral(p, t0, tm), S2 = sigma_integral(p, tm, t1);
+        for (int i = 0; i < n; ++i) {
+          const double mag = exp(-0.25 * h * kap[i]);
+          P1[i] = mag * cexp(I * (0.5 * h * om[i] - S1));
+          P2[i] = mag * cexp(I * (0.5 * h * om[i] - S2));
+        }
+        nonlinear_part(p, yb, k, &rw, !outer);
+        for (int i = 0; i < n; ++i) {
+          yi[i] = P1[i] * yb[i];
+          acc[i] = P1[i] * k[i];
+          u[i] = yi[i] + (0.5 * h) * acc[i];
+        }
+        nonlinear_part(p, u, k, &rw, !outer);
+        for (int i = 0; i < n; ++i) {
+          acc[i] += 2.0 * k[i];
+          u[i] = yi[i] + (0.5 * h) * k[i];
+        }
+        nonlinear_part(p, u, k, &rw, !outer);
+        for (int i = 0; i < n; ++i) {
+          acc[i] += 2.0 * k[i];
+          u[i] = P2[i] * (yi[i] + h * k[i]);
+        }
+        nonlinear_part(p, u, k, &rw, !outer);
+        for (int i = 0; i < n; ++i) yb[i] = P2[i] * (yi[i] + (h / 6.0) * acc[i]) + (h / 6.0) * k[i];
+      }
+    }
+    free(rw.K); free(rw.C); free(P1); free(P2); free(yi); free(u); free(k); free(acc);
   }
   return status;
 }
