@@ -23,7 +23,8 @@ Also reported on the same JSON line:
   fp32          the same sweep in FP32 (FP64 time bookkeeping);
   uneven        the uneven-octave batch (512 instances, N in {1024, ..., 8192},
                 h = 2e-4, 2e4 steps) in FP64 and FP32, classic RK4 on the
-                instances it is stable for (the excluded count is reported);
+                instances it is stable for (the excluded count is reported),
+                and all 512 with the interaction-picture RK4 (FP64);
   staged        the four-step transforms through global memory: 128 x N=8192
                 (beside the LDS-resident kernels), 64 x N=16384, 16 x N=65536,
                 with algorithmic HBM GB/s;
@@ -338,6 +339,18 @@ def uneven_leg(C, W, torch, steps=20000):
             s = timed_run(plan, A, steps, torch)
             out[name] = {"mode_steps_per_s": p.total * steps / s, "seconds": s,
                          "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
+    # all 512 instances, the ones classic RK4 refuses included, with the
+    # interaction-picture RK4 (the linear part integrated exactly)
+    pa = W.pack(wl.instances)
+    with C.Plan(pa, wl.h, integrator=C.CME_RK4IP, flags=C.CME_INIT_AUTOTUNE) as plan:
+        A = plan.state(pa.a0)
+        plan.run(A, 200)
+        torch.cuda.synchronize()
+        s = timed_run(plan, A, steps, torch)
+        out["fp64_rk4ip_all"] = {
+            "instances": pa.batch, "mode_steps_per_s": pa.total * steps / s, "seconds": s,
+            "all_finite": not bool(plan.status().any()),
+            "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
     return out
 
 

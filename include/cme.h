@@ -66,7 +66,7 @@ enum {
 };
 
 enum { CME_F64 = 0, CME_F32 = 1 };        /* arithmetic precision            */
-enum { CME_RK4 = 0, CME_SPLIT_STEP = 2 }; /* integrator                      */
+enum { CME_RK4 = 0, CME_RK4IP = 1, CME_SPLIT_STEP = 2 }; /* integrator       */
 enum {
   CME_FWM_CYCLIC = 0, /* FWM sum taken modulo N (Eq. (4))                       */
   CME_FWM_PADDED = 1  /* FWM sum over the instance's own modes only (the literal
@@ -108,7 +108,13 @@ typedef struct cme_plan cme_plan;
  *   omega  device array [total] of FP64 omega'_mu; copied likewise.
  *   precision CME_F64 or CME_F32 (FP32 state and transforms; the time and
  *          detuning bookkeeping stays FP64).
- *   integrator CME_RK4 (classic fourth-order Runge-Kutta, Sec. 2) or
+ *   integrator CME_RK4 (classic fourth-order Runge-Kutta, Sec. 2),
+ *          CME_RK4IP (interaction-picture RK4, not in the paper: RK4 on
+ *          exp(-int L) A with the linear rate L_mu = -kappa_mu/2 +
+ *          i(omega'_mu - sigma(t)) integrated exactly, the Kerr term and the
+ *          pump through the stages; no RK4 stability check, since the
+ *          dispersion no longer bounds the step; N <= 8192, no adjoint,
+ *          cyclic sum only) or
  *          CME_SPLIT_STEP (frequency-domain Strang split-step, Sec. 2: exact
  *          linear half steps per mode around the exact Kerr phase rotation
  *          of the transformed field; FP64 only, N >= 128, no adjoint).
@@ -194,7 +200,8 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * wavefronts per SIMD, 4: split-step map, 5: RK4 with the padded sum on
  * N-point transforms for instances of N/2 modes, 6: four-step transforms
  * staged through global memory, several workgroups per instance, with the
- * row length N1 in the V field), instances per workgroup,
+ * row length N1 in the V field, 7: interaction-picture RK4 on the
+ * two-level transform), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libcme.so")
 CME_OK, CME_EINVAL, CME_ENOMEM, CME_EHIP = 0, -1, -2, -3
 CME_EUNSTABLE, CME_ENONFINITE, CME_EUNSUPPORTED, CME_ENODEVICE = -4, -5, -6, -7
 CME_F64, CME_F32 = 0, 1
-CME_RK4, CME_SPLIT_STEP = 0, 2
+CME_RK4, CME_RK4IP, CME_SPLIT_STEP = 0, 1, 2
 CME_FWM_CYCLIC, CME_FWM_PADDED = 0, 1
 CME_INIT_DEFAULT, CME_INIT_SKIP_STABILITY, CME_INIT_AUTOTUNE = 0, 1, 2
 
@@ -210,7 +210,7 @@ def cme_kernel_info(kernel_id: int) -> dict:
     info = dict(zip(KERNEL_INFO_FIELDS, (int(x) for x in out)))
     info["id"] = int(kernel_id)
     info["threads_per_instance"] = info["n_modes"] // info["elems_per_thread"]
-    info["name"] = ({0: "rk4_persistent", 1: "rk4_wave", 2: "rk4_duo", 3: "rk4_lean", 4: "split_lean", 5: "rk4_wave_pad", 6: "rk4_staged"}[info["kind"]]
+    info["name"] = ({0: "rk4_persistent", 1: "rk4_wave", 2: "rk4_duo", 3: "rk4_lean", 4: "split_lean", 5: "rk4_wave_pad", 6: "rk4_staged", 7: "rk4ip_wave"}[info["kind"]]
                     + "<{},{},{},{},{}{}>".format(
                         "double" if info["precision"] == 0 else "float", info["n_modes"],
                         info["elems_per_thread"], info["sub_transforms"], info["pad_shift"],

@@ -44,6 +44,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_staged(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_rk4ip(&n);
+    v.insert(v.end(), a, a + n);
     return v;
   }();
   *count = (int)all.size();
@@ -119,12 +121,15 @@ const Variant *all_variants(int *count) { return cme::variants(count); }
 // SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
 // per CU).
 // kind 4 kernels step the split-step map, kind 5 RK4 with the padded sum,
-// all others RK4 with the cyclic sum; `integrator` encodes both choices as
-// integrator + 16 fwm
+// kind 7 interaction-picture RK4, all others RK4 with the cyclic sum;
+// `integrator` encodes both choices as integrator + 16 fwm
 bool integrates(const Variant &v, int integrator) {
   const int fwm = integrator >> 4, integ = integrator & 15;
   if (fwm == CME_FWM_PADDED) return v.kind == 5;
-  return v.kind != 5 && (v.kind == 4) == (integ == CME_SPLIT_STEP);
+  if (v.kind == 5) return false;
+  if (v.kind == 4) return integ == CME_SPLIT_STEP;
+  if (v.kind == 7) return integ == CME_RK4IP;
+  return integ == CME_RK4;
 }
 
 const Variant *default_variant(int precision, int n, int integrator) {
@@ -382,7 +387,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   *plan = nullptr;
   if (batch <= 0 || !inst || !kappa || !omega) return CME_EINVAL;
   if (precision != CME_F64 && precision != CME_F32) return CME_EINVAL;
-  if ((integrator != CME_RK4 && integrator != CME_SPLIT_STEP) ||
+  if ((integrator != CME_RK4 && integrator != CME_RK4IP && integrator != CME_SPLIT_STEP) ||
       (fwm != CME_FWM_CYCLIC && fwm != CME_FWM_PADDED))
     return CME_EINVAL;
   if (integrator == CME_SPLIT_STEP && precision != CME_F64) return CME_EUNSUPPORTED;

@@ -93,7 +93,8 @@ struct Variant {
                    // waves per SIMD (cme_lean.hip), 4: split-step map (cme_split.hip),
                    // 5: RK4 with the padded (alias-free truncated) sum (cme_wave.hip),
                    // 6: RK4 with four-step transforms staged through global memory
-                   // (cme_staged.hip; `v` holds the row length N1)
+                   // (cme_staged.hip; `v` holds the row length N1), 7: interaction-
+                   // picture RK4 (cme_rk4ip.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -111,6 +112,7 @@ const Variant *variants_duo(int *count);   // cme_duo.hip
 const Variant *variants_duo_f32(int *count);  // cme_duo.hip (FP32)
 const Variant *variants_split(int *count); // cme_split.hip
 const Variant *variants_staged(int *count);  // cme_staged.hip
+const Variant *variants_rk4ip(int *count);   // cme_rk4ip.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 }  // namespace cme

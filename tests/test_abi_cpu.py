@@ -62,7 +62,7 @@ def test_kernel_table_covers_every_size():
                 assert info["threads"] % 64 == 0
             else:
                 assert info["threads"] == info["instances_per_group"] * (n // e)
-            if info["kind"] in (1, 2, 3, 4, 5):  # two-level kernels: whole wavefronts per instance
+            if info["kind"] in (1, 2, 3, 4, 5, 7):  # two-level kernels: whole wavefronts per instance
                 assert (n // e) % 64 == 0
             seen.add(k)
         # above 8192 only the staged kernels
@@ -98,7 +98,7 @@ def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan
                                   "reserved", "neg_offset", "overlap", "bad_flags",
                                   "nan_sigma", "neg_kext", "bad_integrator", "split_fp32",
                                   "bad_fwm", "padded_split", "large_fp32", "large_split",
-                                  "large_padded"])
+                                  "large_padded", "rk4ip_padded"])
 def test_init_rejects_invalid_arguments_without_a_device(case):
     kappa = np.ones(256)
     omega = np.zeros(256)
@@ -138,7 +138,11 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
     elif case == "neg_kext":
         inst = _inst(kappa_ext=-0.1)
     elif case == "bad_integrator":
-        kw["integrator"] = 1
+        kw["integrator"] = 3
+    elif case == "rk4ip_padded":
+        kw["integrator"] = C.CME_RK4IP
+        kw["fwm"] = C.CME_FWM_PADDED
+        expect = C.CME_EUNSUPPORTED
     elif case == "bad_fwm":
         kw["fwm"] = 2
     elif case == "padded_split":

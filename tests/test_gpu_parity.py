@@ -65,7 +65,7 @@ def _variant_params():
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
                 for k in C.cme_list_kernels(C.CME_F64, n)
-                if C.cme_kernel_info(k)["kind"] not in (4, 5)]
+                if C.cme_kernel_info(k)["kind"] not in (4, 5, 7)]
     except Exception:
         return [(16, 0)]
 
@@ -243,7 +243,7 @@ def _variant_params_f32():
     try:
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
-                for k in C.cme_list_kernels(C.CME_F32, n)]
+                for k in C.cme_list_kernels(C.CME_F32, n) if C.cme_kernel_info(k)["kind"] != 7]
     except Exception:
         return [(16, 0)]
 

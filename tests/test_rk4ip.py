@@ -131,3 +131,150 @@ def test_rk4ip_agrees_with_classic_rk4_where_both_are_accurate(orc):
     for b in range(p.batch):
         assert diffs[1][b] <= 1e-7 and moved[b] > 1e-2
         assert 12.0 < diffs[0][b] / diffs[1][b] < 20.0
+
+
+# ---------------------------------------------------------------------------
+# GPU (HIP solver through the C ABI)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cme():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1307_3428_amd import cme as C
+    C.load_library()
+    return C
+
+
+def gpu_ip(C, p, h, steps, step0=0, precision=0, kid=None, ckpt_every=0):
+    import torch
+    with C.Plan(p, h, precision=precision, integrator=C.CME_RK4IP) as plan:
+        n = int(p.n_modes[0])
+        if kid is not None:
+            plan.select(n, kid)
+        A = plan.state(p.a0)
+        ck = None
+        if ckpt_every:
+            ck = torch.zeros((steps // ckpt_every, p.total), dtype=A.dtype, device=A.device)
+        plan.run(A, steps, step0=step0, ckpt_every=ckpt_every, ckpt=ck)
+        torch.cuda.synchronize()
+        st = plan.status()
+        name = plan.kernel(n)["name"]
+        out = A.cpu().numpy().astype(np.complex128)
+        return out, (ck.cpu().numpy() if ck is not None else None), st, name
+
+
+def _ip_params(precision):
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096, 8192)
+                for k in C.cme_list_kernels(precision, n) if C.cme_kernel_info(k)["kind"] == 7]
+    except Exception:
+        return [(128, 0)]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,kid", _ip_params(0))
+def test_gpu_rk4ip_variant_matches_oracle(cme, orc, n, kid):
+    batch = 5 if cme.cme_kernel_info(kid)["instances_per_group"] > 1 else 2
+    p = W.pack(nonlinear_batch(3000 + n, [n] * batch))
+    h, steps = 0.01, 4
+    y, _, st, name = gpu_ip(cme, p, h, steps, step0=5, kid=kid)
+    ref = orc.rk4ip_run(p, h, steps, step0=5)
+    errs = [rel_err(y[p.slice(b)], ref[p.slice(b)]) for b in range(batch)]
+    print(name, errs, flush=True)
+    assert max(errs) <= 1e-13 and not st.any()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,kid", _ip_params(1))
+def test_gpu_rk4ip_fp32_variant_matches_fp64_oracle(cme, orc, n, kid):
+    batch = 5 if cme.cme_kernel_info(kid)["instances_per_group"] > 1 else 2
+    p = W.pack(nonlinear_batch(3100 + n, [n] * batch))
+    h, steps = 0.01, 4
+    y, _, st, name = gpu_ip(cme, p, h, steps, step0=5, precision=1, kid=kid)
+    ref = orc.rk4ip_run(p, h, steps, step0=5)
+    errs = [rel_err(y[p.slice(b)], ref[p.slice(b)]) for b in range(batch)]
+    print(name, errs, flush=True)
+    assert max(errs) <= 2e-6 and not st.any()
+
+
+@pytest.mark.gpu
+def test_gpu_rk4ip_undriven_linear_problem_is_exact(cme):
+    """N = 2048 with max |omega'| h ~ 10: the closed-form propagator, no oracle."""
+    insts = stiff_linear_batch(7, n=2048, batch=2)
+    for b, inst in enumerate(insts):
+        inst.omega = W.dispersion_profile(2048, d2=8e-3 + 1e-3 * b)
+    p = W.pack(insts)
+    h, steps = 2e-3, 250
+    T = h * steps
+    assert max(np.abs(p.omega)) * h > 2 * math.sqrt(2)
+    y, _, st, name = gpu_ip(cme, p, h, steps)
+    for b, inst in enumerate(insts):
+        exact = inst.a0 * np.exp(-0.5 * inst.kappa * T + 1j * (inst.omega * T - sigma_quad(inst, 0.0, T)))
+        err = rel_err(y[p.slice(b)], exact)
+        print(f"{name} instance {b}: vs closed form {err:.2e}")
+        assert err <= 1e-11
+    assert not st.any()
+
+
+def _unstable_uneven(count):
+    wl = W.uneven_octave(n_steps=1)
+    bad = []
+    for inst in wl.instances:
+        for sg in (inst.sigma0, inst.sigma1):
+            z = wl.h * (-0.5 * inst.kappa + 1j * (inst.omega - sg))
+            if np.any(np.abs(1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24) > 1 + 1e-12):
+                bad.append(inst)
+                break
+    return wl, bad[:count]
+
+
+@pytest.mark.gpu
+def test_gpu_rk4ip_runs_the_instances_classic_rk4_refuses(cme, orc):
+    """Uneven-octave instances past the classic RK4 bound: cme_init refuses
+    them for CME_RK4 and accepts them for CME_RK4IP; 10 steps against the
+    oracle's RK4IP, then 2000 more stay finite with bounded power."""
+    import torch
+    wl, bad = _unstable_uneven(3)
+    assert len(bad) == 3
+    p = W.pack(bad)
+    with pytest.raises(cme.CmeError):
+        cme.Plan(p, wl.h)
+    y, _, st, name = gpu_ip(cme, p, wl.h, 10)
+    ref = orc.rk4ip_run(p, wl.h, 10)
+    errs = [rel_err(y[p.slice(b)], ref[p.slice(b)]) for b in range(p.batch)]
+    print(name, errs, flush=True)
+    assert max(errs) <= 1e-12 and not st.any()
+    with cme.Plan(p, wl.h, integrator=cme.CME_RK4IP) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 2000)
+        torch.cuda.synchronize()
+        a = A.cpu().numpy()
+        assert not plan.status().any() and np.all(np.isfinite(a))
+        for b, inst in enumerate(bad):
+            # the Kerr and detuning terms conserve P = sum |A|^2, so
+            # dP/dt <= -kappa_min P + 2 |s| sqrt(P) (s = sqrt(kappa_ext) A_in):
+            # P stays below (2 |s| / kappa_min)^2 when it starts there
+            bound = (2 * math.sqrt(inst.kappa_ext) * abs(inst.a_in) / inst.kappa.min()) ** 2
+            assert np.sum(np.abs(inst.a0) ** 2) < bound
+            assert np.sum(np.abs(a[p.slice(b)]) ** 2) < 1.001 * bound
+
+
+@pytest.mark.gpu
+def test_gpu_rk4ip_split_runs_and_checkpoints_are_bitwise(cme):
+    import torch
+    p = W.pack(nonlinear_batch(3200, [1024, 1024]))
+    with cme.Plan(p, 0.004, integrator=cme.CME_RK4IP) as plan:
+        A = plan.state(p.a0)
+        ck = torch.zeros((3, p.total), dtype=A.dtype, device=A.device)
+        plan.run(A, 12, step0=2, ckpt_every=4, ckpt=ck)
+        B = plan.state(p.a0)
+        mids = []
+        for s in range(3):
+            plan.run(B, 4, step0=2 + 4 * s)
+            mids.append(B.clone())
+        torch.cuda.synchronize()
+        assert torch.equal(A, B)
+        for s in range(3):
+            assert torch.equal(ck[s], mids[s])
