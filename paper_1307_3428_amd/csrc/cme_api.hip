@@ -3,10 +3,12 @@
 // A plan owns: the per-instance device descriptors, copies of the per-mode
 // loss and frequency arrays, one twiddle table exp(-2 pi i k / N) per mode
 // count (computed on the host in long double), the per-size launch order,
-// the non-finite flags and, on first use, the adjoint's scratch.
-// Instances are grouped by mode count; each group runs as one persistent
-// launch of the kernel variant chosen for that size (fixed table, or the
-// fastest variant measured once when CME_INIT_AUTOTUNE is set).
+// the non-finite flags, the staged kernels' workspace and, on first use, the
+// adjoint's scratch.  Instances are grouped by transform length; each group
+// runs as one persistent launch of the kernel variant chosen for that size
+// (eight launches per step for the staged kernels), the groups concurrently
+// on forked streams; the variant comes from a fixed table, or is the fastest
+// measured once when CME_INIT_AUTOTUNE is set.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -112,14 +114,6 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 const Variant *all_variants(int *count) { return cme::variants(count); }
 
-// The default kernel for a size is the first compiled variant listed for it
-// (the tables list the preferred shape first).
-// Default kernel of a size when the plan is not autotuned: the first
-// variant of that size in table order (the paired-transform kernels come
-// first; their tables list the preferred shape first), except that the lean
-// kernel is preferred where its eight wavefronts per instance fill two per
-// SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
-// per CU).
 // kind 4 kernels step the split-step map, kind 5 RK4 with the padded sum,
 // kind 7 interaction-picture RK4, all others RK4 with the cyclic sum;
 // `integrator` encodes both choices as integrator + 16 fwm
@@ -132,6 +126,12 @@ bool integrates(const Variant &v, int integrator) {
   return integ == CME_RK4;
 }
 
+// Default kernel of a size when the plan is not autotuned: the first
+// variant of that size in table order (the paired-transform kernels come
+// first; their tables list the preferred shape first), except that the lean
+// kernel is preferred where its eight wavefronts per instance fill two per
+// SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
+// per CU).
 const Variant *default_variant(int precision, int n, int integrator) {
   int cnt = 0;
   const Variant *v = all_variants(&cnt);
