@@ -205,7 +205,8 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
- * twiddles are held in registers).  Returns 10, or CME_EINVAL. */
+ * twiddles are held in registers; kind 6: wavefronts per workgroup).
+ * Returns 10, or CME_EINVAL. */
 int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 
 /* Release the plan and everything it owns.  NULL is accepted. */

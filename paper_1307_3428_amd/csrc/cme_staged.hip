@@ -252,12 +252,13 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
 template <int N, int N1, int E, int WPB> constexpr Variant staged_variant() {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
-  return Variant{0, N, E, N1, kPS, 0, 6, 1, 64 * WPB,
+  return Variant{0, N, E, N1, kPS, WPB, 6, 1, 64 * WPB,
                  CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES,
                  &launch_staged<N, N1, E, WPB>, nullptr, 3};
 }
 
-// (N, N1, E, waves per workgroup); the field `v` of a variant holds N1.  The
+// (N, N1, E, waves per workgroup); the field `v` of a variant holds N1 and
+// `tp` the waves per workgroup.  The
 // first of a size is its default: eight waves per workgroup measured 1-7%
 // faster than four.
 const Variant kStagedVariants[] = {
