@@ -17,7 +17,8 @@
 //       a_4 = V_3 + h i g0 b_3
 //   R3: K'_3, K'_4             (forward transforms of b_3 and b_4)
 //       k_3, u_4, W_4, k_4;  y += h/6 (k_1 + 2 k_2 + 2 k_3 + k_4).
-// Only y, the RK4 accumulator and W_3 live across rounds.
+// Only two arrays live across rounds R2 and R3: y + h W_3 and
+// y + h/6 (k_1 + 2 k_2 + 2 W_3), which stand for y, the accumulator and W_3.
 // Eight transforms in four rounds; the two of a round have the same
 // direction and structure, so their passes are interleaved: while one
 // transform's LDS exchange is in flight the wave computes the other's
@@ -381,7 +382,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
-  cx<Real> y[E], acc[E], w3[E], va[E], vb[E];
+  cx<Real> y[E], yw[E], va[E], vb[E];
   Real lr[E];
   double om[E];
   sfor<0, E>([&](auto mi) {
@@ -463,12 +464,17 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       rec_u(n, 1, mi, u2);
       const cx<Real> w2 = lin(u2, mi, s2);
       const cx<Real> k2 = {w2.re - gn * vb[m].im, w2.im + gn * vb[m].re};
-      acc[m] = {k1.re + (Real)2 * k2.re, k1.im + (Real)2 * k2.im};
       const cx<Real> u3 = {y[m].re + hh * k2.re, y[m].im + hh * k2.im};
       rec_u(n, 2, mi, u3);
-      w3[m] = lin(u3, mi, s2);
+      const cx<Real> w3 = lin(u3, mi, s2);
+      // from here on y + h W_3 and y + h/6 (k_1 + 2 k_2 + 2 W_3) stand for y,
+      // the accumulator and W_3: u_4 = yw + h i (g0/N) K'_3 and
+      // y' = y + h/6 (k_1 + 2 k_2 + 2 W_3) + h/6 (2 i (g0/N) K'_3 + k_4)
+      yw[m] = {y[m].re + hf * w3.re, y[m].im + hf * w3.im};
+      y[m] = {y[m].re + h6 * (k1.re + (Real)2 * (k2.re + w3.re)),
+              y[m].im + h6 * (k1.im + (Real)2 * (k2.im + w3.im))};
       va[m] = u3;
-      vb[m] = {y[m].re + hf * w3[m].re, y[m].im + hf * w3[m].im};
+      vb[m] = yw[m];
     });
     // ---- R2: a_3 = IDFT(u_3), IDFT(y + h W_3)
     lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
@@ -486,14 +492,13 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
     lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      const cx<Real> k3 = {w3[m].re - gn * va[m].im, w3[m].im + gn * va[m].re};
-      const cx<Real> u4 = {y[m].re + hf * k3.re, y[m].im + hf * k3.im};
+      // i (g0/N) K'_3
+      const cx<Real> q3 = {-gn * va[m].im, gn * va[m].re};
+      const cx<Real> u4 = {yw[m].re + hf * q3.re, yw[m].im + hf * q3.im};
       rec_u(n, 3, mi, u4);
       const cx<Real> w4 = lin(u4, mi, s4);
       const cx<Real> k4 = {w4.re - gn * vb[m].im, w4.im + gn * vb[m].re};
-      const cx<Real> ac = {acc[m].re + (Real)2 * k3.re + k4.re,
-                           acc[m].im + (Real)2 * k3.im + k4.im};
-      y[m] = {y[m].re + h6 * ac.re, y[m].im + h6 * ac.im};
+      y[m] = {y[m].re + h6 * ((Real)2 * q3.re + k4.re), y[m].im + h6 * ((Real)2 * q3.im + k4.im)};
     });
     if (ckpt != nullptr && --to_ckpt == 0) {
       to_ckpt = a.ckpt_every;
