@@ -128,20 +128,13 @@ bool integrates(const Variant &v, int integrator) {
 
 // Default kernel of a size when the plan is not autotuned: the first
 // variant of that size in table order (the paired-transform kernels come
-// first; their tables list the preferred shape first), except that the lean
-// kernel is preferred where its eight wavefronts per instance fill two per
-// SIMD (N = 4096 at E = 8, 2.5x the wave kernel's throughput at one instance
-// per CU).
+// first; their tables list the preferred shape first).
 const Variant *default_variant(int precision, int n, int integrator) {
   int cnt = 0;
   const Variant *v = all_variants(&cnt);
-  const Variant *first = nullptr;
-  for (int i = 0; i < cnt; ++i) {
-    if (v[i].precision != precision || v[i].n != n || !integrates(v[i], integrator)) continue;
-    if (v[i].kind == 3 && v[i].threads >= 512) return &v[i];
-    if (!first) first = &v[i];
-  }
-  return first;
+  for (int i = 0; i < cnt; ++i)
+    if (v[i].precision == precision && v[i].n == n && integrates(v[i], integrator)) return &v[i];
+  return nullptr;
 }
 
 // compiled variants for a precision and size; integrator < 0: any

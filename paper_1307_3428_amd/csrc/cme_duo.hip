@@ -737,11 +737,20 @@ hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
 // registers (1); reported as exchange = NV + 16 FT.  The reverse sweep has
 // more live state and always forms its twiddles (it reads the stage records
 // in the same slot order whatever the forward kernel's twiddle source).
+// Reverse sweep of a paired forward kernel: the paired reverse, except at
+// eight wavefronts per instance (N = 4096), where its registers do not fit
+// two waves per SIMD and the lean reverse, which reads the same stage
+// records, is used.
+template <typename Real, int N, int E, int PS, int NV> constexpr AdjLaunch duo_adj_ptr() {
+  if constexpr (N / (64 * E) >= 8) return &launch_lean_adj<Real, N, E, PS>;
+  else return &launch_duo_adj<Real, N, E, PS, NV, 0>;
+}
+
 template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant duo_variant() {
   using SH = DuoShape<Real, N, E, PS>;
   if constexpr (std::is_same<Real, double>::value)
     return Variant{0, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
-                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, &launch_duo_adj<Real, N, E, PS, NV, 0>};
+                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, duo_adj_ptr<Real, N, E, PS, NV>()};
   else  // FP32 plans have no adjoint
     return Variant{1, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
                    &launch_duo_fwd<Real, N, E, PS, NV, FT>, nullptr};
@@ -749,13 +758,15 @@ template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant
 
 // The first entry of a size is its default.  N = 512 and 1024 run four
 // elements per thread (two and four wavefronts per instance: 39% and 21%
-// faster than the previous defaults at 256 instances); N = 4096 (eight
-// waves per instance) is left to the lean kernel.
+// faster than the previous defaults at 256 instances); N = 4096 runs eight
+// wavefronts per instance, two per SIMD, with the twiddles rebuilt on use
+// (the register-held tables do not fit), 5% faster than the lean kernel.
 static const Variant kDuoVariants[] = {
     duo_variant<double, 512, 4, 2, 4, 1>(),  duo_variant<double, 1024, 4, 2, 5, 1>(),
     duo_variant<double, 1024, 4, 2, 4, 1>(), duo_variant<double, 1024, 8, 3, 4, 1>(),
     duo_variant<double, 2048, 8, 3, 5, 1>(), duo_variant<double, 2048, 8, 3, 4, 1>(),
-    duo_variant<double, 2048, 8, 3, 4, 0>(),
+    duo_variant<double, 2048, 8, 3, 4, 0>(), duo_variant<double, 4096, 8, 3, 4, 0>(),
+    duo_variant<double, 4096, 8, 3, 5, 0>(),
 };
 
 // FP32: the same kernels with FP32 state and transforms (time and detuning
