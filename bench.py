@@ -171,6 +171,13 @@ def main() -> int:
         for j, i in enumerate(pick):
             a, b = y[p.slice(i)], ref[sub.slice(j)]
             errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+        # the same oracle on one core: one instance, 10 steps
+        one = W.pack([wl.instances[pick[0]]])
+        oracle.set_threads(1)
+        t1 = time.perf_counter()
+        oracle.run(one, wl.h, 10)
+        cpu1_s = time.perf_counter() - t1
+        oracle.set_threads(threads)
         parity = {"max_rel_l2_err": max(errs), "instances": pick, "rk4_steps": args.parity_steps,
                   "tolerance": 1e-10, "ok": max(errs) <= 1e-10}
     flags_out = plan.status()
@@ -241,6 +248,8 @@ def main() -> int:
             "kind": "oracle",
             "sample": f"{len(pick)} of the 256 N=2048 instances x {args.parity_steps} RK4 steps "
                       f"(O(N^2) direct-sum FWM, FP64, OpenMP), {cpu_s:.1f} s",
+            "one_core": {"value": 2048 * 10 / cpu1_s, "cores": 1,
+                         "sample": f"1 instance x 10 RK4 steps, {cpu1_s:.2f} s"},
         }
     plan.close()
 
