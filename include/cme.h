@@ -144,6 +144,16 @@ int cme_step(cme_plan *plan, void *A, int64_t step0);
 int cme_run(cme_plan *plan, void *A, int64_t step0, int64_t n_steps,
             int32_t ckpt_every, void *ckpt);
 
+/* The four-wave-mixing sum alone, for every instance of the plan:
+ *   K_mu = sum over alpha - beta + gamma = mu (mod N) of A_alpha conj(A_beta) A_gamma
+ * (Eq. (1) with the cyclic sum of Eq. (4)), evaluated with the library's
+ * transforms as Eq. (4) states it: a = IDFT(A), b = |a|^2 a, K = DFT(b) / N.
+ *   A  device complex [total], read only (packed like the state)
+ *   K  device complex [total], written (same packing; K may not alias A)
+ * Plans with CME_FWM_PADDED: CME_EUNSUPPORTED.  Asynchronous on the plan's
+ * stream.  Exposes steps a3-a5 of the solver for direct tests. */
+int cme_fwm(cme_plan *plan, const void *A, void *K);
+
 /* Discrete adjoint of cme_run (not in the paper: the gradient form of the
  * method).  Given the state A0 at step0 (device complex [total]) and the
  * cotangent gA_T = dL/dRe A(T) + i dL/dIm A(T) of the state after n_steps

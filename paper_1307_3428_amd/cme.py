@@ -27,7 +27,7 @@ CME_FWM_CYCLIC, CME_FWM_PADDED = 0, 1
 CME_INIT_DEFAULT, CME_INIT_SKIP_STABILITY, CME_INIT_AUTOTUNE = 0, 1, 2
 
 EXPORTED = (
-    "cme_init", "cme_step", "cme_run", "cme_adjoint", "cme_status", "cme_set_stream",
+    "cme_init", "cme_step", "cme_run", "cme_fwm", "cme_adjoint", "cme_status", "cme_set_stream",
     "cme_plan_kernel", "cme_plan_select", "cme_list_kernels", "cme_kernel_info", "cme_destroy",
     "cme_strerror", "cme_version",
 )
@@ -74,6 +74,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cme_init": (ctypes.c_int, [ctypes.POINTER(P), i32, P, P, P, i32, i32, i32, dbl, P, u32]),
         "cme_step": (ctypes.c_int, [P, P, i64]),
         "cme_run": (ctypes.c_int, [P, P, i64, i64, i32, P]),
+        "cme_fwm": (ctypes.c_int, [P, P, P]),
         "cme_adjoint": (ctypes.c_int, [P, P, P, i64, i64, i32, P, P, P, P, P]),
         "cme_status": (ctypes.c_int, [P, P]),
         "cme_set_stream": (ctypes.c_int, [P, P]),
@@ -161,6 +162,10 @@ def cme_step(plan: int, A, step0: int) -> None:
 def cme_run(plan: int, A, step0: int, n_steps: int, ckpt_every: int = 0, ckpt=None) -> None:
     _check(load_library().cme_run(plan, _dptr(A), int(step0), int(n_steps), int(ckpt_every),
                                   _dptr(ckpt)), "cme_run")
+
+
+def cme_fwm(plan: int, A, K) -> None:
+    _check(load_library().cme_fwm(plan, _dptr(A), _dptr(K)), "cme_fwm")
 
 
 def cme_adjoint(plan: int, A0, ckpt, step0: int, n_steps: int, ckpt_every: int, gA_T,
@@ -261,6 +266,13 @@ class Plan:
     def step(self, A, step0: int):
         cme_step(self.handle, A, step0)
         return A
+
+    def fwm(self, A, K=None):
+        """The four-wave-mixing sum K of every instance (a new tensor unless K is given)."""
+        if K is None:
+            K = self.torch.empty_like(A)
+        cme_fwm(self.handle, A, K)
+        return K
 
     def adjoint(self, A0, gA_T, n_steps: int, step0: int = 0, ckpt_every: int = 0, ckpt=None,
                 want=("gA_0", "g_omega", "g_kappa", "g_ain")):

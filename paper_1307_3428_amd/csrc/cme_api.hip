@@ -544,6 +544,26 @@ int cme_run(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_e
 
 int cme_step(cme_plan *p, void *A, int64_t step0) { return cme_run(p, A, step0, 1, 0, nullptr); }
 
+int cme_fwm(cme_plan *p, const void *A, void *K) {
+  if (!p || !A || !K) return CME_EINVAL;
+  if (p->fwm != CME_FWM_CYCLIC) return CME_EUNSUPPORTED;
+  const size_t nc = p->classes.size();
+  if (nc > 1) HIP_TRY(hipEventRecord(p->fork, p->stream));
+  for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
+  for (size_t i = 0; i < nc; ++i) {
+    SizeClass &c = p->classes[i];
+    if (c.n > 8192 && !c.d_work) return CME_EUNSUPPORTED;
+    const cme::RunArgs a = run_args(p, c, const_cast<void *>(A), 0, 1, 0, K, nullptr);
+    if (cme::launch_fwm(p->precision, c.n, a, i == 0 ? p->stream : c.side) != hipSuccess)
+      return CME_EHIP;
+  }
+  for (size_t i = 1; i < nc; ++i) {
+    HIP_TRY(hipEventRecord(p->classes[i].done, p->classes[i].side));
+    HIP_TRY(hipStreamWaitEvent(p->stream, p->classes[i].done, 0));
+  }
+  return CME_OK;
+}
+
 int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, int64_t n_steps,
                 int32_t ckpt_every, const void *gA_T, void *gA_0, double *g_omega,
                 double *g_kappa, double *g_ain) {

@@ -115,4 +115,9 @@ const Variant *variants_staged(int *count);  // cme_staged.hip
 const Variant *variants_rk4ip(int *count);   // cme_rk4ip.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
+// The four-wave-mixing sum alone for one size class (cme_fwm.hip): reads the
+// packed amplitudes at a.A and writes K at a.ckpt (same packing); sizes above
+// 8192 use the staged transform and the class workspace a.work.
+hipError_t launch_fwm(int precision, int n, const RunArgs &a, hipStream_t st);
+
 }  // namespace cme

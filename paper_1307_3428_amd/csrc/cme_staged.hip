@@ -92,7 +92,9 @@ template <int N, int N1, int E, int WPB> struct RowShape {
 };
 
 // STAGE < 0: start the inverse transform of the state (first launch of a run);
-// STAGE = s in 0..3: RK4 stage s + 1 as described above.
+// STAGE = s in 0..3: RK4 stage s + 1 as described above; STAGE = 4: finish
+// the forward transform and write the four-wave-mixing sum K = (N K) / N
+// (cme_fwm), packed like the state, to a.ckpt.
 template <int N, int N1, int E, int WPB, int STAGE>
 __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
   using SH = ColShape<N, N1, E, WPB>;
@@ -125,6 +127,14 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
       v[m] = S[(t + m * T) * N1 + m1];
     });
     fft_team<N2, E, -1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+    if constexpr (STAGE == 4) {
+      const double inv_n = 1.0 / (double)N;
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        a.ckpt[d.a_offset + m1 + N1 * (t + m * T)] = {v[m].re * inv_n, v[m].im * inv_n};
+      });
+      return;
+    }
     const double h = a.h;
     const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
     const double *kap = a.kappa + d.offset, *omg = a.omega + d.offset;
@@ -249,6 +259,32 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The four-wave-mixing sum alone (cme_fwm): r.A in, r.ckpt out, through the
+// class workspace.
+template <int N, int N1, int E, int WPB>
+hipError_t fwm_staged(const RunArgs &r, hipStream_t st) {
+  using CS = ColShape<N, N1, E, WPB>;
+  using RS = RowShape<N, N1, E, WPB>;
+  if (r.work == nullptr || r.ckpt == nullptr) return hipErrorInvalidValue;
+  if (r.count <= 0) return hipSuccess;
+  StagedArgs a{};
+  a.inst = r.inst;
+  a.order = r.order;
+  a.count = r.count;
+  a.A = reinterpret_cast<cx<double> *>(r.A);
+  a.kappa = r.kappa;
+  a.omega = r.omega;
+  a.tab = reinterpret_cast<const cx<double> *>(r.twiddle);
+  a.work = reinterpret_cast<cx<double> *>(r.work);
+  a.ckpt = reinterpret_cast<cx<double> *>(r.ckpt);
+  a.flags = r.flags;
+  const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1>), cgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 4>), cgrid, blk, 0, st, a);
+  return hipGetLastError();
+}
+
 template <int N, int N1, int E, int WPB> constexpr Variant staged_variant() {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
@@ -270,6 +306,15 @@ const Variant kStagedVariants[] = {
 };
 
 }  // namespace
+
+hipError_t launch_staged_fwm(int n, const RunArgs &r, hipStream_t st) {
+  switch (n) {
+    case 16384: return fwm_staged<16384, 128, 8, 8>(r, st);
+    case 32768: return fwm_staged<32768, 256, 8, 8>(r, st);
+    case 65536: return fwm_staged<65536, 256, 8, 8>(r, st);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 const Variant *variants_staged(int *count) {
   *count = (int)(sizeof(kStagedVariants) / sizeof(kStagedVariants[0]));

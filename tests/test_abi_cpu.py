@@ -170,6 +170,7 @@ def test_calls_on_null_plan():
     lib = C.load_library()
     assert lib.cme_run(None, None, 0, 1, 0, None) == C.CME_EINVAL
     assert lib.cme_step(None, None, 0) == C.CME_EINVAL
+    assert lib.cme_fwm(None, None, None) == C.CME_EINVAL
     assert lib.cme_adjoint(None, None, None, 0, 1, 0, None, None, None, None, None) == C.CME_EINVAL
     flags = np.zeros(1, np.int32)
     assert lib.cme_status(None, flags.ctypes.data_as(ctypes.c_void_p)) == C.CME_EINVAL
