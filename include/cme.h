@@ -17,7 +17,9 @@
  * the mode amplitudes, the pointwise cube |a|^2 a, and a forward transform
  * carrying the single 1/N; both transforms run as FFTs inside the GPU kernels.
  * Time stepping is the classic fourth-order Runge-Kutta scheme named in
- * Sec. 2 (stage times t, t+h/2, t+h/2, t+h; weights 1/6, 1/3, 1/3, 1/6).
+ * Sec. 2 (stage times t, t+h/2, t+h/2, t+h; weights 1/6, 1/3, 1/3, 1/6);
+ * cme_init also offers the paper's frequency-domain split-step method and
+ * an interaction-picture RK4, and cme_fwm evaluates K alone.
  *
  * Conventions shared by every entry point
  *   - An instance is one resonator.  Its N mode amplitudes are stored
