@@ -76,6 +76,18 @@ __host__ __device__ inline double sigma_at(double sigma0, double sigma1, double 
   return sigma0 + (sigma1 - sigma0) * (s / tau_ramp);
 }
 
+// integral of sigma(t) over [a, b], 0 <= a <= b, for the ramp of sigma_at
+// (the interaction-picture kernels' exact linear propagators)
+__host__ __device__ inline double sigma_integral(double s0, double s1, double tau, double a,
+                                                 double b) {
+  if (!(tau > 0.0)) return s0 * (b - a);
+  double ramp;  // integral of min(t, tau)
+  if (b <= tau) ramp = 0.5 * (b - a) * (b + a);
+  else if (a >= tau) ramp = tau * (b - a);
+  else ramp = 0.5 * (tau - a) * (tau + a) + tau * (b - tau);
+  return s0 * (b - a) + (s1 - s0) / tau * ramp;
+}
+
 using FwdLaunch = hipError_t (*)(const RunArgs &, hipStream_t);
 using AdjLaunch = hipError_t (*)(const AdjArgs &, hipStream_t);
 
@@ -94,7 +106,8 @@ struct Variant {
                    // 5: RK4 with the padded (alias-free truncated) sum (cme_wave.hip),
                    // 6: RK4 with four-step transforms staged through global memory
                    // (cme_staged.hip; `v` holds the row length N1), 7: interaction-
-                   // picture RK4 (cme_rk4ip.hip)
+                   // picture RK4 (cme_rk4ip.hip), 8: interaction-picture RK4 on the
+                   // staged transforms (cme_staged.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -113,6 +126,7 @@ const Variant *variants_duo_f32(int *count);  // cme_duo.hip (FP32)
 const Variant *variants_split(int *count); // cme_split.hip
 const Variant *variants_staged(int *count);  // cme_staged.hip
 const Variant *variants_rk4ip(int *count);   // cme_rk4ip.hip
+const Variant *variants_staged_ip(int *count);  // cme_staged.hip (interaction picture)
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 // The four-wave-mixing sum alone for one size class (cme_fwm.hip): reads the

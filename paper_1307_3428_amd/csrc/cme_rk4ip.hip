@@ -24,16 +24,6 @@ namespace cme {
 
 namespace {
 
-// integral of sigma(t) over [a, b], 0 <= a <= b, for the ramp of sigma_at
-__device__ double sigma_integral(double s0, double s1, double tau, double a, double b) {
-  if (!(tau > 0.0)) return s0 * (b - a);
-  double ramp;  // integral of min(t, tau)
-  if (b <= tau) ramp = 0.5 * (b - a) * (b + a);
-  else if (a >= tau) ramp = tau * (b - a);
-  else ramp = 0.5 * (tau - a) * (tau + a) + tau * (b - tau);
-  return s0 * (b - a) + (s1 - s0) / tau * ramp;
-}
-
 template <typename Real, int N, int E, int V, int PS, int TP>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) rk4ip_wave(RunArgs a) {
   using SH = WaveShape<Real, N, E, V, PS, TP>;

@@ -91,11 +91,18 @@ template <int N, int N1, int E, int WPB> struct RowShape {
   static_assert(T >= 1 && T <= 64 && N2 % R == 0, "row shape");
 };
 
+// IP: the interaction-picture RK4 instead (the linear part exact): per step
+// from t0, with P1, P2 = exp((-kappa/2 + i omega') h/2 - i int sigma) over the
+// two half steps and N(u) = i (g0/N) N K + pump,
+//   stage 1: yI = P1 y -> U, k1 = P1 N(y) -> ACC, next yI + h/2 k1;
+//   stage 2: k2 = N(u2), ACC += 2 k2, next yI + h/2 k2;
+//   stage 3: k3 = N(u3), ACC += 2 k3, next P2 (yI + h k3);
+//   stage 4: k4 = N(u4), y' = P2 (yI + h/6 ACC) + h/6 k4.
 // STAGE < 0: start the inverse transform of the state (first launch of a run);
 // STAGE = s in 0..3: RK4 stage s + 1 as described above; STAGE = 4: finish
 // the forward transform and write the four-wave-mixing sum K = (N K) / N
 // (cme_fwm), packed like the state, to a.ckpt.
-template <int N, int N1, int E, int WPB, int STAGE>
+template <int N, int N1, int E, int WPB, int STAGE, bool IP = false>
 __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
   using SH = ColShape<N, N1, E, WPB>;
   constexpr int N2 = SH::N2, T = SH::T;
@@ -136,9 +143,53 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
       return;
     }
     const double h = a.h;
-    const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
     const double *kap = a.kappa + d.offset, *omg = a.omega + d.offset;
     bool bad = false;
+    if constexpr (IP) {
+      // detuning phase of the half step whose propagator this stage applies
+      const double tm = a.t0 + 0.5 * h;
+      const double sg = STAGE == 0 ? sigma_integral(d.sigma0, d.sigma1, d.tau_ramp, a.t0, tm)
+                                   : sigma_integral(d.sigma0, d.sigma1, d.tau_ramp, tm, a.t0 + h);
+      auto prop = [&](int i) {  // P = exp(-kappa h/4) exp(i (omega' h/2 - int sigma))
+        const double mag = exp(-0.25 * h * kap[i]);
+        double sn, cs;
+        sincos(0.5 * h * omg[i] - sg, &sn, &cs);
+        return cx<double>{mag * cs, mag * sn};
+      };
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        const int i = m1 + N1 * (t + m * T);
+        cx<double> k = {-d.g0n * v[m].im, d.g0n * v[m].re};
+        if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
+        cx<double> nxt;
+        if constexpr (STAGE == 0) {
+          const cx<double> p1 = prop(i);
+          const cx<double> yi = cmul(p1, A[i]);
+          const cx<double> k1 = cmul(p1, k);
+          ACC[i] = k1;
+          U[i] = yi;
+          nxt = {yi.re + 0.5 * h * k1.re, yi.im + 0.5 * h * k1.im};
+        } else if constexpr (STAGE == 1) {
+          const cx<double> yi = U[i], acc = ACC[i];
+          ACC[i] = {acc.re + 2.0 * k.re, acc.im + 2.0 * k.im};
+          nxt = {yi.re + 0.5 * h * k.re, yi.im + 0.5 * h * k.im};
+        } else if constexpr (STAGE == 2) {
+          const cx<double> yi = U[i], acc = ACC[i];
+          ACC[i] = {acc.re + 2.0 * k.re, acc.im + 2.0 * k.im};
+          nxt = cmul(prop(i), cx<double>{yi.re + h * k.re, yi.im + h * k.im});
+        } else {
+          const cx<double> yi = U[i], acc = ACC[i];
+          const double c = h / 6.0;
+          const cx<double> z = cmul(prop(i), cx<double>{yi.re + c * acc.re, yi.im + c * acc.im});
+          nxt = {z.re + c * k.re, z.im + c * k.im};
+          A[i] = nxt;
+          if (a.ckpt) a.ckpt[d.a_offset + i] = nxt;
+          bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
+        }
+        v[m] = nxt;
+      });
+    } else {
+    const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const int i = m1 + N1 * (t + m * T);
@@ -169,6 +220,7 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
       }
       v[m] = nxt;
     });
+    }
     if constexpr (STAGE == 3) {
       if (bad) atomicOr(&a.flags[id], 1);
       if (a.tail) return;
@@ -220,7 +272,7 @@ __global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgs a) {
   });
 }
 
-template <int N, int N1, int E, int WPB>
+template <int N, int N1, int E, int WPB, bool IP = false>
 hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
@@ -240,7 +292,7 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
   cx<double> *ck = reinterpret_cast<cx<double> *>(r.ckpt);
   a.t0 = (double)r.step0 * r.h;
-  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1>), cgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1, IP>), cgrid, blk, 0, st, a);
   int64_t slot = 0;
   for (int64_t n = 0; n < r.n_steps; ++n) {
     a.t0 = (double)(r.step0 + n) * r.h;
@@ -248,13 +300,13 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
     if (ck && r.ckpt_every > 0 && (n + 1) % r.ckpt_every == 0) a.ckpt = ck + (slot++) * r.total;
     a.tail = n + 1 == r.n_steps;
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0, IP>), cgrid, blk, 0, st, a);
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1, IP>), cgrid, blk, 0, st, a);
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2, IP>), cgrid, blk, 0, st, a);
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3, IP>), cgrid, blk, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -285,12 +337,12 @@ hipError_t fwm_staged(const RunArgs &r, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int N, int N1, int E, int WPB> constexpr Variant staged_variant() {
+template <int N, int N1, int E, int WPB, bool IP = false> constexpr Variant staged_variant() {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
-  return Variant{0, N, E, N1, kPS, WPB, 6, 1, 64 * WPB,
+  return Variant{0, N, E, N1, kPS, WPB, IP ? 8 : 6, 1, 64 * WPB,
                  CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES,
-                 &launch_staged<N, N1, E, WPB>, nullptr, 3};
+                 &launch_staged<N, N1, E, WPB, IP>, nullptr, 3};
 }
 
 // (N, N1, E, waves per workgroup); the field `v` of a variant holds N1 and
@@ -305,6 +357,12 @@ const Variant kStagedVariants[] = {
     staged_variant<65536, 256, 8, 4>(),
 };
 
+// interaction-picture RK4 on the same transforms (kind 8)
+const Variant kStagedIpVariants[] = {
+    staged_variant<8192, 128, 8, 8, true>(),  staged_variant<16384, 128, 8, 8, true>(),
+    staged_variant<32768, 256, 8, 8, true>(), staged_variant<65536, 256, 8, 8, true>(),
+};
+
 }  // namespace
 
 hipError_t launch_staged_fwm(int n, const RunArgs &r, hipStream_t st) {
@@ -314,6 +372,11 @@ hipError_t launch_staged_fwm(int n, const RunArgs &r, hipStream_t st) {
     case 65536: return fwm_staged<65536, 256, 8, 8>(r, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+const Variant *variants_staged_ip(int *count) {
+  *count = (int)(sizeof(kStagedIpVariants) / sizeof(kStagedIpVariants[0]));
+  return kStagedIpVariants;
 }
 
 const Variant *variants_staged(int *count) {

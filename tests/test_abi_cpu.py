@@ -54,7 +54,7 @@ def test_kernel_table_covers_every_size():
             e = info["elems_per_thread"]
             assert e & (e - 1) == 0 and 2 <= e <= n
             assert info["threads"] <= 1024 and info["lds_bytes"] <= 160 * 1024
-            if info["kind"] == 6:
+            if info["kind"] in (6, 8):
                 # staged: rows of N1 and columns of N / N1 points, each a
                 # team of whole lanes inside one wavefront
                 n1 = info["sub_transforms"]
@@ -66,7 +66,7 @@ def test_kernel_table_covers_every_size():
                 assert (n // e) % 64 == 0
             seen.add(k)
         # above 8192 only the staged kernels
-        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] == 6 for k in ids)
+        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8) for k in ids)
         assert n <= 8192 or C.cme_list_kernels(C.CME_F32, n) == []
     assert C.cme_list_kernels(C.CME_F64, 100) == []
     assert C.cme_list_kernels(C.CME_F64, 131072) == []

@@ -167,8 +167,8 @@ def gpu_ip(C, p, h, steps, step0=0, precision=0, kid=None, ckpt_every=0):
 def _ip_params(precision):
     try:
         from paper_1307_3428_amd import cme as C
-        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096, 8192)
-                for k in C.cme_list_kernels(precision, n) if C.cme_kernel_info(k)["kind"] == 7]
+        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536)
+                for k in C.cme_list_kernels(precision, n) if C.cme_kernel_info(k)["kind"] in (7, 8)]
     except Exception:
         return [(128, 0)]
 
@@ -177,8 +177,11 @@ def _ip_params(precision):
 @pytest.mark.parametrize("n,kid", _ip_params(0))
 def test_gpu_rk4ip_variant_matches_oracle(cme, orc, n, kid):
     batch = 5 if cme.cme_kernel_info(kid)["instances_per_group"] > 1 else 2
+    steps = 4
+    if n >= 32768:   # the oracle's O(N^2) sum costs seconds per evaluation here
+        batch, steps = 1, 2
     p = W.pack(nonlinear_batch(3000 + n, [n] * batch))
-    h, steps = 0.01, 4
+    h = 0.01
     y, _, st, name = gpu_ip(cme, p, h, steps, step0=5, kid=kid)
     ref = orc.rk4ip_run(p, h, steps, step0=5)
     errs = [rel_err(y[p.slice(b)], ref[p.slice(b)]) for b in range(batch)]
@@ -200,11 +203,13 @@ def test_gpu_rk4ip_fp32_variant_matches_fp64_oracle(cme, orc, n, kid):
 
 
 @pytest.mark.gpu
-def test_gpu_rk4ip_undriven_linear_problem_is_exact(cme):
-    """N = 2048 with max |omega'| h ~ 10: the closed-form propagator, no oracle."""
-    insts = stiff_linear_batch(7, n=2048, batch=2)
+@pytest.mark.parametrize("n", [2048, 16384])
+def test_gpu_rk4ip_undriven_linear_problem_is_exact(cme, n):
+    """max |omega'| h ~ 10: the closed-form propagator, no oracle (N = 16384:
+    the staged transforms)."""
+    insts = stiff_linear_batch(7, n=n, batch=2)
     for b, inst in enumerate(insts):
-        inst.omega = W.dispersion_profile(2048, d2=8e-3 + 1e-3 * b)
+        inst.omega = W.dispersion_profile(n, d2=(8e-3 + 1e-3 * b) * (2048 / n) ** 2)
     p = W.pack(insts)
     h, steps = 2e-3, 250
     T = h * steps
