@@ -17,6 +17,10 @@ pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-10
 
+# kernel kinds that step classic RK4 with the cyclic sum (the others: split-step,
+# padded sum, interaction-picture RK4, tested in their own files)
+RK4_KINDS = (0, 1, 2, 3, 6)
+
 
 @pytest.fixture(scope="module")
 def cme():
@@ -65,7 +69,7 @@ def _variant_params():
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
                 for k in C.cme_list_kernels(C.CME_F64, n)
-                if C.cme_kernel_info(k)["kind"] not in (4, 5, 7)]
+                if C.cme_kernel_info(k)["kind"] in RK4_KINDS]
     except Exception:
         return [(16, 0)]
 
@@ -243,7 +247,7 @@ def _variant_params_f32():
     try:
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192)
-                for k in C.cme_list_kernels(C.CME_F32, n) if C.cme_kernel_info(k)["kind"] != 7]
+                for k in C.cme_list_kernels(C.CME_F32, n) if C.cme_kernel_info(k)["kind"] in RK4_KINDS]
     except Exception:
         return [(16, 0)]
 
