@@ -27,7 +27,7 @@ Also reported on the same JSON line:
                 and all 512 with the interaction-picture RK4 (FP64);
   staged        the four-step transforms through global memory: 128 x N=8192
                 (beside the LDS-resident kernels), 64 x N=16384, 16 x N=65536,
-                with algorithmic HBM GB/s;
+                with algorithmic HBM GB/s, for RK4 and for the split-step map;
   padded        256 instances of N = 1024 with the alias-free truncated sum
                 (2N-point transforms) beside the cyclic sum, 2000 steps;
   fig1          the paper's Fig. 1 ensemble (four N = 256 runs to normalised
@@ -368,6 +368,9 @@ def uneven_leg(C, W, torch, steps=20000):
 # omega' and writes S (+ u, acc; y at the last stage); the row kernel reads
 # and writes S.  16 B per complex value, 8 per real.
 STAGED_BYTES_PER_MODE_STEP = (16 * 5 + 16) + 2 * (16 * 7 + 16) + (16 * 6 + 16) + 4 * 32
+# split-step on the staged transforms: the row kernel reads and writes S, the
+# column kernel reads and writes S and reads kappa and omega'
+SPLIT_STAGED_BYTES_PER_MODE_STEP = 32 + 32 + 16
 
 
 def staged_leg(C, W, torch, only=0, steps=None):
@@ -398,6 +401,20 @@ def staged_leg(C, W, torch, only=0, steps=None):
                 gbps = rate * STAGED_BYTES_PER_MODE_STEP / 1e9
                 case.update({"algorithmic_GBps": gbps, "frac_hbm_peak": gbps / 8000.0})
             out["cases"].append(case)
+        if only:
+            continue
+        # the split-step map on the same transforms: two launches per step
+        with C.Plan(p, 2e-4, integrator=C.CME_SPLIT_STEP) as plan:
+            A = plan.state(p.a0)
+            plan.run(A, 10)
+            torch.cuda.synchronize()
+            s = timed_run(plan, A, 4 * nsteps, torch)
+            rate = p.total * 4 * nsteps / s
+            gbps = rate * SPLIT_STAGED_BYTES_PER_MODE_STEP / 1e9
+            out["cases"].append({"workload": f"{b} x N={n}, {4 * nsteps} split steps",
+                                 "kernel": plan.kernel(n)["name"], "mode_steps_per_s": rate,
+                                 "us_per_step": 1e6 * s / (4 * nsteps), "algorithmic_GBps": gbps,
+                                 "frac_hbm_peak": gbps / 8000.0})
     return out
 
 

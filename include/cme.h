@@ -25,8 +25,8 @@
  *   - An instance is one resonator.  Its N mode amplitudes are stored
  *     contiguously in centred order: element i holds mode mu = i - N/2, so the
  *     pump mode mu = 0 is element N/2.  N must be a power of two,
- *     16 <= N <= 65536; above 8192 only FP64 RK4 or RK4IP with the cyclic
- *     sum is supported (CME_EUNSUPPORTED otherwise).
+ *     16 <= N <= 65536; above 8192 only FP64 with the cyclic sum is
+ *     supported (CME_EUNSUPPORTED otherwise).
  *   - A batch packs instances back to back; instance b starts at element
  *     inst[b].mode_offset of every per-mode array (state, kappa, omega').
  *     Ranges of different instances must not overlap.  "total" below is the
@@ -214,11 +214,12 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * staged through global memory, several workgroups per instance, with the
  * row length N1 in the V field, 7: interaction-picture RK4 on the
  * two-level transform, 8: interaction-picture RK4 on the staged
- * transforms), instances per workgroup,
+ * transforms, 9: split-step map on the staged transforms), instances per
+ * workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
- * twiddles are held in registers; kinds 6 and 8: wavefronts per workgroup).
+ * twiddles are held in registers; kinds 6, 8, 9: wavefronts per workgroup).
  * Returns 10, or CME_EINVAL. */
 int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 

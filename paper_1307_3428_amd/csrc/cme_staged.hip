@@ -311,6 +311,183 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The split-step map (Sec. 2, the second method) on the same transforms.  A
+// step from t0: exact linear half step with sigma frozen at t0 + h/4, a =
+// IDFT(y), the exact Kerr rotation a e^{i g0 h |a|^2}, y = DFT(a) / N, exact
+// linear half step with sigma at t0 + 3h/4.  Two launches per step:
+//   row kernel: finish the inverse transform, rotate, start the forward one;
+//   column kernel: finish the forward transform, the step's second half step
+//   (and its checkpoint), the next step's first half step, start the next
+//   inverse transform.
+// MODE 0: first launch of a run (first half step of the first step);
+// MODE 1: between steps; MODE 2: last step of the run (result to the state).
+// ---------------------------------------------------------------------------
+
+// y e^{L dt} + [pump mode] s (e^{L dt} - 1) / L with L = -kappa/2 + i(omega' - sigma)
+__device__ __forceinline__ cx<double> linear_exact(cx<double> y, double kap, double om, double sig,
+                                                   double dt, bool pump_mode, cx<double> s) {
+  const double lre = -0.5 * kap, lim = om - sig;
+  const double mag = exp(lre * dt);
+  double sn, cs;
+  sincos(lim * dt, &sn, &cs);
+  const cx<double> e = {mag * cs, mag * sn};
+  cx<double> out = cmul(y, e);
+  if (pump_mode) {
+    cx<double> phi;  // (e - 1) / L, or its small-|L dt| limit
+    if (sqrt(lre * lre + lim * lim) * dt > 1e-8) {
+      const double den = lre * lre + lim * lim;
+      phi = {((e.re - 1.0) * lre + e.im * lim) / den, (e.im * lre - (e.re - 1.0) * lim) / den};
+    } else {
+      phi = {dt * (1.0 + 0.5 * lre * dt), dt * (0.5 * lim * dt)};
+    }
+    out = cadd(out, cmul(s, phi));
+  }
+  return out;
+}
+
+template <int N, int N1, int E, int WPB, int MODE>
+__global__ void __launch_bounds__(64 * WPB) split_col(StagedArgs a) {
+  using SH = ColShape<N, N1, E, WPB>;
+  constexpr int N2 = SH::N2, T = SH::T;
+  __shared__ cx<double> lds[WPB * SH::CW * SH::LB];
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x / SH::NB, cb = (int)blockIdx.x % SH::NB;
+  const int cl = lane % SH::CW, t = lane / SH::CW;
+  const int m1 = cb * SH::C + wv * SH::CW + cl;
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  cx<double> *A = a.A + d.a_offset;
+  cx<double> *S = a.work + (int64_t)slot * 3 * N;
+  cx<double> *buf = lds + (wv * SH::CW + cl) * SH::LB;
+  const double *kap = a.kappa + d.offset, *omg = a.omega + d.offset;
+  const cx<double> s = {d.pump_re, d.pump_im};
+  const double h = a.h, hh = 0.5 * a.h;
+
+  cx<double> tw[FftPlan<N2, E>::NTW];
+  load_twiddles<N2, E, N1>(tw, a.tab, t);
+  cx<double> v[E];
+  if constexpr (MODE == 0) {
+    const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + 0.25 * h);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const int i = m1 + N1 * (t + m * T);
+      v[m] = linear_exact(A[i], kap[i], omg[i], sig, hh, i == N / 2, s);
+    });
+  } else {
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      v[m] = S[(t + m * T) * N1 + m1];
+    });
+    fft_team<N2, E, -1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+    const double inv_n = 1.0 / (double)N;
+    const double sig2 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + 0.75 * h);
+    const double sig1 = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + 1.25 * h);
+    bool bad = false;
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const int i = m1 + N1 * (t + m * T);
+      const cx<double> y2 = {v[m].re * inv_n, v[m].im * inv_n};
+      const cx<double> yn = linear_exact(y2, kap[i], omg[i], sig2, hh, i == N / 2, s);
+      if (a.ckpt) a.ckpt[d.a_offset + i] = yn;
+      if constexpr (MODE == 2) {
+        A[i] = yn;
+        bad |= !(isfinite(yn.re) && isfinite(yn.im));
+      } else {
+        v[m] = linear_exact(yn, kap[i], omg[i], sig1, hh, i == N / 2, s);
+      }
+    });
+    if constexpr (MODE == 2) {
+      if (bad) atomicOr(&a.flags[id], 1);
+      return;
+    }
+  }
+  fft_team<N2, E, +1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+  cx<double> xw[E];
+  cross_tw<N, E, T>(xw, a.tab, m1, t);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    S[(t + m * T) * N1 + m1] = cmulc(v[m], xw[m]);
+  });
+}
+
+template <int N, int N1, int E, int WPB>
+__global__ void __launch_bounds__(64 * WPB) split_row(StagedArgs a) {
+  using SH = RowShape<N, N1, E, WPB>;
+  constexpr int T = SH::T;
+  __shared__ cx<double> lds[WPB * SH::RW * SH::LB];
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x / SH::NB, rb = (int)blockIdx.x % SH::NB;
+  const int team = lane / T, t = lane % T;
+  const int j2 = rb * SH::R + wv * SH::RW + team;
+  const DevInst d = a.inst[a.order[slot]];
+  cx<double> *S = a.work + (int64_t)slot * 3 * N + (int64_t)j2 * N1;
+  cx<double> *buf = lds + (wv * SH::RW + team) * SH::LB;
+  const double gh = d.g0n * (double)N * a.h;  // g0 h
+
+  cx<double> tw[FftPlan<N1, E>::NTW];
+  load_twiddles<N1, E, N / N1>(tw, a.tab, t);
+  cx<double> v[E];
+  sfor<0, E>([&](auto mi) { v[decltype(mi)::value] = S[t + decltype(mi)::value * T]; });
+  fft_team<N1, E, +1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    double sn, cs;
+    sincos(gh * (v[m].re * v[m].re + v[m].im * v[m].im), &sn, &cs);
+    v[m] = cmul(v[m], cx<double>{cs, sn});
+  });
+  fft_team<N1, E, -1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
+  cx<double> xw[E];
+  cross_tw<N, E, T>(xw, a.tab, j2, t);
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    S[t + m * T] = cmul(v[m], xw[m]);
+  });
+}
+
+template <int N, int N1, int E, int WPB>
+hipError_t launch_split_staged(const RunArgs &r, hipStream_t st) {
+  using CS = ColShape<N, N1, E, WPB>;
+  using RS = RowShape<N, N1, E, WPB>;
+  if (r.stages != nullptr || r.work == nullptr) return hipErrorInvalidValue;
+  if (r.count <= 0 || r.n_steps <= 0) return hipSuccess;
+  StagedArgs a{};
+  a.inst = r.inst;
+  a.order = r.order;
+  a.count = r.count;
+  a.A = reinterpret_cast<cx<double> *>(r.A);
+  a.kappa = r.kappa;
+  a.omega = r.omega;
+  a.tab = reinterpret_cast<const cx<double> *>(r.twiddle);
+  a.work = reinterpret_cast<cx<double> *>(r.work);
+  a.h = r.h;
+  a.flags = r.flags;
+  const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
+  cx<double> *ck = reinterpret_cast<cx<double> *>(r.ckpt);
+  a.t0 = (double)r.step0 * r.h;
+  hipLaunchKernelGGL((split_col<N, N1, E, WPB, 0>), cgrid, blk, 0, st, a);
+  int64_t slot = 0;
+  for (int64_t n = 0; n < r.n_steps; ++n) {
+    a.t0 = (double)(r.step0 + n) * r.h;
+    a.ckpt = nullptr;
+    if (ck && r.ckpt_every > 0 && (n + 1) % r.ckpt_every == 0) a.ckpt = ck + (slot++) * r.total;
+    hipLaunchKernelGGL((split_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
+    if (n + 1 == r.n_steps)
+      hipLaunchKernelGGL((split_col<N, N1, E, WPB, 2>), cgrid, blk, 0, st, a);
+    else
+      hipLaunchKernelGGL((split_col<N, N1, E, WPB, 1>), cgrid, blk, 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+template <int N, int N1, int E, int WPB> constexpr Variant split_staged_variant() {
+  using CS = ColShape<N, N1, E, WPB>;
+  using RS = RowShape<N, N1, E, WPB>;
+  return Variant{0, N, E, N1, kPS, WPB, 9, 1, 64 * WPB,
+                 CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES,
+                 &launch_split_staged<N, N1, E, WPB>, nullptr, 3};
+}
+
 // The four-wave-mixing sum alone (cme_fwm): r.A in, r.ckpt out, through the
 // class workspace.
 template <int N, int N1, int E, int WPB>
@@ -357,6 +534,12 @@ const Variant kStagedVariants[] = {
     staged_variant<65536, 256, 8, 4>(),
 };
 
+// split-step map on the same transforms (kind 9)
+const Variant kStagedSplitVariants[] = {
+    split_staged_variant<8192, 128, 8, 8>(),  split_staged_variant<16384, 128, 8, 8>(),
+    split_staged_variant<32768, 256, 8, 8>(), split_staged_variant<65536, 256, 8, 8>(),
+};
+
 // interaction-picture RK4 on the same transforms (kind 8)
 const Variant kStagedIpVariants[] = {
     staged_variant<8192, 128, 8, 8, true>(),  staged_variant<16384, 128, 8, 8, true>(),
@@ -372,6 +555,11 @@ hipError_t launch_staged_fwm(int n, const RunArgs &r, hipStream_t st) {
     case 65536: return fwm_staged<65536, 256, 8, 8>(r, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+const Variant *variants_staged_split(int *count) {
+  *count = (int)(sizeof(kStagedSplitVariants) / sizeof(kStagedSplitVariants[0]));
+  return kStagedSplitVariants;
 }
 
 const Variant *variants_staged_ip(int *count) {

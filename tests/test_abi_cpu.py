@@ -54,7 +54,7 @@ def test_kernel_table_covers_every_size():
             e = info["elems_per_thread"]
             assert e & (e - 1) == 0 and 2 <= e <= n
             assert info["threads"] <= 1024 and info["lds_bytes"] <= 160 * 1024
-            if info["kind"] in (6, 8):
+            if info["kind"] in (6, 8, 9):
                 # staged: rows of N1 and columns of N / N1 points, each a
                 # team of whole lanes inside one wavefront
                 n1 = info["sub_transforms"]
@@ -66,7 +66,7 @@ def test_kernel_table_covers_every_size():
                 assert (n // e) % 64 == 0
             seen.add(k)
         # above 8192 only the staged kernels
-        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8) for k in ids)
+        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8, 9) for k in ids)
         assert n <= 8192 or C.cme_list_kernels(C.CME_F32, n) == []
     assert C.cme_list_kernels(C.CME_F64, 100) == []
     assert C.cme_list_kernels(C.CME_F64, 131072) == []
@@ -97,8 +97,8 @@ def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan
                                   "n_too_small", "neg_h", "nan_h", "bad_precision",
                                   "reserved", "neg_offset", "overlap", "bad_flags",
                                   "nan_sigma", "neg_kext", "bad_integrator", "split_fp32",
-                                  "bad_fwm", "padded_split", "large_fp32", "large_split",
-                                  "large_padded", "rk4ip_padded"])
+                                  "bad_fwm", "padded_split", "large_fp32", "large_padded",
+                                  "rk4ip_padded"])
 def test_init_rejects_invalid_arguments_without_a_device(case):
     kappa = np.ones(256)
     omega = np.zeros(256)
@@ -149,11 +149,10 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
         kw["fwm"] = C.CME_FWM_PADDED
         kw["integrator"] = C.CME_SPLIT_STEP
         expect = C.CME_EUNSUPPORTED
-    elif case in ("large_fp32", "large_split", "large_padded"):
-        # above 8192 transform points only FP64 RK4 with the cyclic sum
+    elif case in ("large_fp32", "large_padded"):
+        # above 8192 transform points only FP64 with the cyclic sum
         inst = _inst(n=16384 if case != "large_padded" else 8192)
         kw.update({"large_fp32": {"precision": C.CME_F32},
-                   "large_split": {"integrator": C.CME_SPLIT_STEP},
                    "large_padded": {"fwm": C.CME_FWM_PADDED}}[case])
         expect = C.CME_EUNSUPPORTED
     elif case == "split_fp32":

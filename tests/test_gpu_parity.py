@@ -388,8 +388,8 @@ def test_concurrent_classes_match_separate_plans(cme):
 def _split_params():
     try:
         from paper_1307_3428_amd import cme as C
-        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096)
-                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] == 4]
+        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536)
+                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] in (4, 9)]
     except Exception:
         return [(128, 0)]
 
@@ -400,8 +400,10 @@ def test_split_step_variant_matches_oracle(cme, orc, n, kid):
     info = cme.cme_kernel_info(kid)
     print(f"variant {info['name']}", flush=True)
     batch = 5 if info["instances_per_group"] > 1 else 2
-    p = W.pack(moderate_batch(5000 + n, [n] * batch))
     steps, h = 20, 0.01
+    if n > 8192:   # the oracle's naive O(N^2) transforms cost seconds here
+        batch, steps = (2, 4) if n <= 16384 else (1, 2)
+    p = W.pack(moderate_batch(5000 + n, [n] * batch))
     with cme.Plan(p, h, integrator=cme.CME_SPLIT_STEP) as plan:
         plan.select(n, kid)
         A = plan.state(p.a0)
@@ -433,7 +435,7 @@ def test_split_step_fig1_ensemble(cme, orc):
 
 def test_split_step_checkpoints_and_split_runs(cme):
     import torch
-    p = W.pack(moderate_batch(13, [256, 2048, 128]))
+    p = W.pack(moderate_batch(13, [256, 2048, 128, 16384]))
     with cme.Plan(p, 0.01, integrator=cme.CME_SPLIT_STEP) as plan:
         A = plan.state(p.a0)
         ck = torch.zeros((2, p.total), dtype=torch.complex128, device="cuda")
