@@ -111,7 +111,7 @@ def main() -> int:
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this solver benchmark runs on exactly one GPU; independent instances "
-              "would be sharded across GPUs with no communication, which this build does not "
+              "would be sharded across GPUs with no communication, which this benchmark does not "
               "launch. Run with --gpus 1.", file=sys.stderr)
         return 2
 

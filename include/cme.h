@@ -63,7 +63,7 @@ enum {
                             h * max_mu |-kappa_mu/2 + i(omega'_mu - sigma)|
                             > 2 sqrt(2) for some instance and detuning      */
   CME_ENONFINITE = -5,   /* non-finite input (kappa, omega', pump, ...)    */
-  CME_EUNSUPPORTED = -6, /* valid request this build does not provide      */
+  CME_EUNSUPPORTED = -6, /* valid request the library does not provide     */
   CME_ENODEVICE = -7     /* no gfx950 device / kernels not loadable        */
 };
 

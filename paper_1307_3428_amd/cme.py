@@ -65,7 +65,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() first")
+        raise RuntimeError(f"{path} is not built; run python -m paper_1307_3428_amd._build first")
     import torch  # noqa: F401  (must precede the dlopen below)
     lib = ctypes.CDLL(path)
     P, i32, i64, u32, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
