@@ -144,6 +144,54 @@ def test_sweep_full_launch_sampled(cme, orc):
     assert not st.any()
 
 
+def _uneven_samples(insts, per_size=2):
+    pick = []
+    for n in (1024, 2048, 4096, 8192):
+        pick += [i for i, x in enumerate(insts) if x.n_modes == n][:per_size]
+    return pick
+
+
+def test_uneven_octave_full_launch_sampled(cme, orc):
+    """The uneven-octave batch (the 485 instances classic RK4 is stable for,
+    four size classes launched concurrently) for 20 steps; two instances per
+    size against the oracle."""
+    wl = W.uneven_octave(n_steps=20)
+    keep = [x for x in wl.instances if rk4_stable(x, wl.h)]
+    p = W.pack(keep)
+    y, st = gpu_run(cme, p, wl.h, wl.n_steps)
+    pick = _uneven_samples(keep)
+    sub = W.pack([keep[i] for i in pick])
+    ref, _ = orc.run(sub, wl.h, wl.n_steps)
+    for j, i in enumerate(pick):
+        err = rel_err(y[p.slice(i)], ref[sub.slice(j)])
+        print(f"N={keep[i].n_modes} instance {i}: {err:.2e}", flush=True)
+        assert err <= 1e-12, (i, err)
+    assert not st.any()
+
+
+def test_uneven_octave_all_instances_rk4ip_sampled(cme, orc):
+    """All 512 uneven-octave instances (the 27 classic RK4 refuses included)
+    with the interaction-picture RK4 in one plan, 10 steps; two instances per
+    size and two refused ones against the oracle's RK4IP."""
+    import torch
+    wl = W.uneven_octave(n_steps=10)
+    p = W.pack(wl.instances)
+    with cme.Plan(p, wl.h, integrator=cme.CME_RK4IP) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, wl.n_steps)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        assert not plan.status().any()
+    refused = [i for i, x in enumerate(wl.instances) if not rk4_stable(x, wl.h)][:2]
+    pick = _uneven_samples(wl.instances) + refused
+    sub = W.pack([wl.instances[i] for i in pick])
+    ref = orc.rk4ip_run(sub, wl.h, wl.n_steps)
+    for j, i in enumerate(pick):
+        err = rel_err(y[p.slice(i)], ref[sub.slice(j)])
+        print(f"N={wl.instances[i].n_modes} instance {i}: {err:.2e}", flush=True)
+        assert err <= 1e-12, (i, err)
+
+
 def test_split_run_is_bitwise(cme):
     import torch
     insts = moderate_batch(5, [256, 2048, 64])
