@@ -133,6 +133,21 @@ def test_staged_agrees_with_lds_kernel_over_a_longer_run(cme):
         assert not st.any()
 
 
+def test_staged_longer_horizon_matches_oracle(cme, orc):
+    """N = 8192 on the staged kernels for 100 steps (the state moves by tens
+    of percent) against the oracle, checkpoints included."""
+    p = W.pack(moderate_batch(71, [8192]))
+    kid = staged_ids(cme, 8192)[0]
+    y, ck, st, names = run(cme, p, 2e-3, 100, select={8192: kid}, ckpt_every=50)
+    ref, ref_ck = orc.run(p, 2e-3, 100, ckpt_every=50)
+    err = rel_err(y, ref)
+    moved = rel_err(p.a0, ref)
+    cerr = max(rel_err(ck[j], ref_ck[j]) for j in range(2))
+    print(f"{names[8192]}: {err:.2e} (moved {moved:.2e}), checkpoints {cerr:.2e}")
+    assert err <= 1e-11 and cerr <= 1e-11 and moved > 0.1
+    assert not st.any()
+
+
 def test_staged_split_runs_and_checkpoints_are_bitwise(cme):
     import torch
     p = W.pack(moderate_batch(53, [16384, 16384]))
