@@ -25,8 +25,8 @@
  *   - An instance is one resonator.  Its N mode amplitudes are stored
  *     contiguously in centred order: element i holds mode mu = i - N/2, so the
  *     pump mode mu = 0 is element N/2.  N must be a power of two,
- *     16 <= N <= 65536; above 8192 only FP64 with the cyclic sum is
- *     supported (CME_EUNSUPPORTED otherwise).
+ *     16 <= N <= 65536; above 8192 the cyclic sum only, in FP64 with any
+ *     integrator or in FP32 with classic RK4 (CME_EUNSUPPORTED otherwise).
  *   - A batch packs instances back to back; instance b starts at element
  *     inst[b].mode_offset of every per-mode array (state, kappa, omega').
  *     Ranges of different instances must not overlap.  "total" below is the
@@ -152,7 +152,8 @@ int cme_run(cme_plan *plan, void *A, int64_t step0, int64_t n_steps,
  * transforms as Eq. (4) states it: a = IDFT(A), b = |a|^2 a, K = DFT(b) / N.
  *   A  device complex [total], read only (packed like the state)
  *   K  device complex [total], written (same packing; K may not alias A)
- * Plans with CME_FWM_PADDED: CME_EUNSUPPORTED.  Asynchronous on the plan's
+ * Plans with CME_FWM_PADDED, and FP32 plans with N > 8192: CME_EUNSUPPORTED.
+ * Asynchronous on the plan's
  * stream.  Exposes steps a3-a5 of the solver for direct tests. */
 int cme_fwm(cme_plan *plan, const void *A, void *K);
 

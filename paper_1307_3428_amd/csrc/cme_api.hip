@@ -395,11 +395,11 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   int64_t total = 0;
   int rc = validate_instances(batch, inst, &total);
   if (rc != CME_OK) return rc;
-  // transforms longer than 8192 points run only on the staged FP64 kernels
-  // (any integrator, cyclic sum)
+  // transforms longer than 8192 points run only on the staged kernels: the
+  // cyclic sum, FP64 with any integrator or FP32 with classic RK4
   for (int32_t b = 0; b < batch; ++b)
     if ((fwm == CME_FWM_PADDED ? 2 : 1) * inst[b].n_modes > 8192 &&
-        (precision != CME_F64 || fwm != CME_FWM_CYCLIC))
+        (fwm != CME_FWM_CYCLIC || (precision != CME_F64 && integrator != CME_RK4)))
       return CME_EUNSUPPORTED;
 
   int device = 0;
@@ -557,7 +557,7 @@ int cme_fwm(cme_plan *p, const void *A, void *K) {
   for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
   for (size_t i = 0; i < nc; ++i) {
     SizeClass &c = p->classes[i];
-    if (c.n > 8192 && !c.d_work) return CME_EUNSUPPORTED;
+    if (c.n > 8192 && (!c.d_work || p->precision != CME_F64)) return CME_EUNSUPPORTED;
     const cme::RunArgs a = run_args(p, c, const_cast<void *>(A), 0, 1, 0, K, nullptr);
     if (cme::launch_fwm(p->precision, c.n, a, i == 0 ? p->stream : c.side) != hipSuccess)
       return CME_EHIP;

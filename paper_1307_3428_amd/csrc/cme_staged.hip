@@ -27,6 +27,8 @@
 // Each team transforms its column or row with the radix-E Stockham passes of
 // cme_fft.hpp in registers, exchanging through a private LDS buffer inside
 // one wavefront (no workgroup barrier).
+#include <type_traits>
+
 #include "cme_fft.hpp"
 #include "cme_internal.hpp"
 
@@ -34,21 +36,31 @@ namespace cme {
 
 namespace {
 
-struct StagedArgs {
+// Real: the precision of the state, the transforms and the stored arrays
+// (FP64, or FP32 for classic RK4); the stage arithmetic is done in FP64.
+template <typename Real> struct StagedArgsT {
   const DevInst *inst;
   const int32_t *order;
   int32_t count;
   int32_t tail;            // column kernel, last stage of the run: no next transform
-  cx<double> *A;           // caller's packed state
+  cx<Real> *A;             // caller's packed state
   const double *kappa;
   const double *omega;
-  const cx<double> *tab;   // exp(-2 pi i k / N), k < N
-  cx<double> *work;        // per class slot: S, acc, u (3 N each)
+  const cx<Real> *tab;     // exp(-2 pi i k / N), k < N
+  cx<Real> *work;          // per class slot: S, acc, u (3 N each)
   double h;
   double t0;               // time at the start of the step
-  cx<double> *ckpt;        // checkpoint row for this step (packed like A) or null
+  cx<Real> *ckpt;          // checkpoint row for this step (packed like A) or null
   int32_t *flags;
 };
+using StagedArgs = StagedArgsT<double>;
+
+template <typename Real> __device__ __forceinline__ cx<double> up(cx<Real> z) {
+  return {(double)z.re, (double)z.im};
+}
+template <typename Real> __device__ __forceinline__ cx<Real> dn(cx<double> z) {
+  return {(Real)z.re, (Real)z.im};
+}
 
 constexpr int kPS = 3;  // one LDS pad element every 8
 
@@ -56,9 +68,9 @@ constexpr int kPS = 3;  // one LDS pad element every 8
 // elements of a thread, as w^{-a b} w^{-a T m}: the second factor is the same
 // for every lane of a team, so a wavefront gathers a few distinct table
 // entries instead of one per lane and element; one complex product each.
-template <int N, int E, int T>
-__device__ __forceinline__ void cross_tw(cx<double> (&tw)[E], const cx<double> *tab, int a, int b) {
-  const cx<double> base = tab[(a * b) & (N - 1)];
+template <int N, int E, int T, typename Real>
+__device__ __forceinline__ void cross_tw(cx<Real> (&tw)[E], const cx<Real> *tab, int a, int b) {
+  const cx<Real> base = tab[(a * b) & (N - 1)];
   tw[0] = base;
   sfor<1, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
@@ -102,25 +114,26 @@ template <int N, int N1, int E, int WPB> struct RowShape {
 // STAGE = s in 0..3: RK4 stage s + 1 as described above; STAGE = 4: finish
 // the forward transform and write the four-wave-mixing sum K = (N K) / N
 // (cme_fwm), packed like the state, to a.ckpt.
-template <int N, int N1, int E, int WPB, int STAGE, bool IP = false>
-__global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
+template <int N, int N1, int E, int WPB, int STAGE, bool IP = false, typename Real = double>
+__global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
   using SH = ColShape<N, N1, E, WPB>;
   constexpr int N2 = SH::N2, T = SH::T;
-  __shared__ cx<double> lds[WPB * SH::CW * SH::LB];
+  static_assert(!IP || std::is_same<Real, double>::value, "the interaction picture is FP64");
+  __shared__ cx<Real> lds[WPB * SH::CW * SH::LB];
   const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
   const int slot = (int)blockIdx.x / SH::NB, cb = (int)blockIdx.x % SH::NB;
   const int cl = lane % SH::CW, t = lane / SH::CW;
   const int m1 = cb * SH::C + wv * SH::CW + cl;
   const int id = a.order[slot];
   const DevInst d = a.inst[id];
-  cx<double> *A = a.A + d.a_offset;
-  cx<double> *S = a.work + (int64_t)slot * 3 * N;
-  cx<double> *ACC = S + N, *U = S + 2 * N;
-  cx<double> *buf = lds + (wv * SH::CW + cl) * SH::LB;
+  cx<Real> *A = a.A + d.a_offset;
+  cx<Real> *S = a.work + (int64_t)slot * 3 * N;
+  cx<Real> *ACC = S + N, *U = S + 2 * N;
+  cx<Real> *buf = lds + (wv * SH::CW + cl) * SH::LB;
 
-  cx<double> tw[FftPlan<N2, E>::NTW];
+  cx<Real> tw[FftPlan<N2, E>::NTW];
   load_twiddles<N2, E, N1>(tw, a.tab, t);
-  cx<double> v[E];
+  cx<Real> v[E];
 
   if constexpr (STAGE < 0) {
     sfor<0, E>([&](auto mi) {
@@ -138,7 +151,7 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
       const double inv_n = 1.0 / (double)N;
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
-        a.ckpt[d.a_offset + m1 + N1 * (t + m * T)] = {v[m].re * inv_n, v[m].im * inv_n};
+        a.ckpt[d.a_offset + m1 + N1 * (t + m * T)] = dn<Real>({v[m].re * inv_n, v[m].im * inv_n});
       });
       return;
     }
@@ -193,32 +206,33 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const int i = m1 + N1 * (t + m * T);
-      const cx<double> y = A[i];
-      const cx<double> u = STAGE == 0 ? y : U[i];
+      const cx<double> y = up(A[i]);
+      const cx<double> u = STAGE == 0 ? y : up(U[i]);
+      const cx<double> nk = up(v[m]);
       const double lr = -0.5 * kap[i], li = omg[i] - sig;
       // k = L u + i (g0/N) N K
-      cx<double> k = {lr * u.re - li * u.im - d.g0n * v[m].im, lr * u.im + li * u.re + d.g0n * v[m].re};
+      cx<double> k = {lr * u.re - li * u.im - d.g0n * nk.im, lr * u.im + li * u.re + d.g0n * nk.re};
       if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
       cx<double> nxt;
       if constexpr (STAGE == 0) {
-        ACC[i] = k;
+        ACC[i] = dn<Real>(k);
         nxt = {y.re + 0.5 * h * k.re, y.im + 0.5 * h * k.im};
-        U[i] = nxt;
+        U[i] = dn<Real>(nxt);
       } else if constexpr (STAGE < 3) {
-        const cx<double> acc = ACC[i];
-        ACC[i] = {acc.re + 2.0 * k.re, acc.im + 2.0 * k.im};
+        const cx<double> acc = up(ACC[i]);
+        ACC[i] = dn<Real>({acc.re + 2.0 * k.re, acc.im + 2.0 * k.im});
         const double c = STAGE == 1 ? 0.5 * h : h;
         nxt = {y.re + c * k.re, y.im + c * k.im};
-        U[i] = nxt;
+        U[i] = dn<Real>(nxt);
       } else {
-        const cx<double> acc = ACC[i];
+        const cx<double> acc = up(ACC[i]);
         const double c = h / 6.0;
         nxt = {y.re + c * (acc.re + k.re), y.im + c * (acc.im + k.im)};
-        A[i] = nxt;
-        if (a.ckpt) a.ckpt[d.a_offset + i] = nxt;
+        A[i] = dn<Real>(nxt);
+        if (a.ckpt) a.ckpt[d.a_offset + i] = dn<Real>(nxt);
         bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
       }
-      v[m] = nxt;
+      v[m] = dn<Real>(nxt);
     });
     }
     if constexpr (STAGE == 3) {
@@ -228,7 +242,7 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
   }
   // inner sum of the inverse transform over m2, times w^{+j2 m1}
   fft_team<N2, E, +1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
-  cx<double> xw[E];
+  cx<Real> xw[E];
   cross_tw<N, E, T>(xw, a.tab, m1, t);
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
@@ -236,21 +250,21 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgs a) {
   });
 }
 
-template <int N, int N1, int E, int WPB>
-__global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgs a) {
+template <int N, int N1, int E, int WPB, typename Real = double>
+__global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgsT<Real> a) {
   using SH = RowShape<N, N1, E, WPB>;
   constexpr int T = SH::T;
-  __shared__ cx<double> lds[WPB * SH::RW * SH::LB];
+  __shared__ cx<Real> lds[WPB * SH::RW * SH::LB];
   const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
   const int slot = (int)blockIdx.x / SH::NB, rb = (int)blockIdx.x % SH::NB;
   const int team = lane / T, t = lane % T;
   const int j2 = rb * SH::R + wv * SH::RW + team;
-  cx<double> *S = a.work + (int64_t)slot * 3 * N + (int64_t)j2 * N1;
-  cx<double> *buf = lds + (wv * SH::RW + team) * SH::LB;
+  cx<Real> *S = a.work + (int64_t)slot * 3 * N + (int64_t)j2 * N1;
+  cx<Real> *buf = lds + (wv * SH::RW + team) * SH::LB;
 
-  cx<double> tw[FftPlan<N1, E>::NTW];
+  cx<Real> tw[FftPlan<N1, E>::NTW];
   load_twiddles<N1, E, N / N1>(tw, a.tab, t);
-  cx<double> v[E];
+  cx<Real> v[E];
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
     v[m] = S[t + m * T];
@@ -259,12 +273,12 @@ __global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgs a) {
   fft_team<N1, E, +1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    const double p = v[m].re * v[m].re + v[m].im * v[m].im;
+    const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
     v[m] = {p * v[m].re, p * v[m].im};
   });
   // inner sum of the forward transform over j1, times w^{-j2 m1}
   fft_team<N1, E, -1, kPS, false, 0, SYNC_WAVE>(v, buf, buf, tw, t);
-  cx<double> xw[E];
+  cx<Real> xw[E];
   cross_tw<N, E, T>(xw, a.tab, j2, t);
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
@@ -272,41 +286,41 @@ __global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgs a) {
   });
 }
 
-template <int N, int N1, int E, int WPB, bool IP = false>
+template <int N, int N1, int E, int WPB, bool IP = false, typename Real = double>
 hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
   if (r.stages != nullptr || r.work == nullptr) return hipErrorInvalidValue;
   if (r.count <= 0 || r.n_steps <= 0) return hipSuccess;
-  StagedArgs a{};
+  StagedArgsT<Real> a{};
   a.inst = r.inst;
   a.order = r.order;
   a.count = r.count;
-  a.A = reinterpret_cast<cx<double> *>(r.A);
+  a.A = reinterpret_cast<cx<Real> *>(r.A);
   a.kappa = r.kappa;
   a.omega = r.omega;
-  a.tab = reinterpret_cast<const cx<double> *>(r.twiddle);
-  a.work = reinterpret_cast<cx<double> *>(r.work);
+  a.tab = reinterpret_cast<const cx<Real> *>(r.twiddle);
+  a.work = reinterpret_cast<cx<Real> *>(r.work);
   a.h = r.h;
   a.flags = r.flags;
   const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
-  cx<double> *ck = reinterpret_cast<cx<double> *>(r.ckpt);
+  cx<Real> *ck = reinterpret_cast<cx<Real> *>(r.ckpt);
   a.t0 = (double)r.step0 * r.h;
-  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1, IP>), cgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1, IP, Real>), cgrid, blk, 0, st, a);
   int64_t slot = 0;
   for (int64_t n = 0; n < r.n_steps; ++n) {
     a.t0 = (double)(r.step0 + n) * r.h;
     a.ckpt = nullptr;
     if (ck && r.ckpt_every > 0 && (n + 1) % r.ckpt_every == 0) a.ckpt = ck + (slot++) * r.total;
     a.tail = n + 1 == r.n_steps;
-    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0, IP>), cgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1, IP>), cgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2, IP>), cgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3, IP>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3, IP, Real>), cgrid, blk, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -514,12 +528,14 @@ hipError_t fwm_staged(const RunArgs &r, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int N, int N1, int E, int WPB, bool IP = false> constexpr Variant staged_variant() {
+template <int N, int N1, int E, int WPB, bool IP = false, typename Real = double>
+constexpr Variant staged_variant() {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
-  return Variant{0, N, E, N1, kPS, WPB, IP ? 8 : 6, 1, 64 * WPB,
-                 CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES,
-                 &launch_staged<N, N1, E, WPB, IP>, nullptr, 3};
+  constexpr int scale = 16 / (int)sizeof(cx<Real>);  // the shapes count 16-byte elements
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, N1, kPS, WPB, IP ? 8 : 6, 1,
+                 64 * WPB, (CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES) / scale,
+                 &launch_staged<N, N1, E, WPB, IP, Real>, nullptr, 3};
 }
 
 // (N, N1, E, waves per workgroup); the field `v` of a variant holds N1 and
@@ -532,6 +548,9 @@ const Variant kStagedVariants[] = {
     staged_variant<16384, 128, 8, 4>(), staged_variant<32768, 256, 8, 8>(),
     staged_variant<32768, 256, 8, 4>(), staged_variant<65536, 256, 8, 8>(),
     staged_variant<65536, 256, 8, 4>(),
+    // FP32 state and transforms (FP64 stage arithmetic)
+    staged_variant<8192, 128, 8, 8, false, float>(),  staged_variant<16384, 128, 8, 8, false, float>(),
+    staged_variant<32768, 256, 8, 8, false, float>(), staged_variant<65536, 256, 8, 8, false, float>(),
 };
 
 // split-step map on the same transforms (kind 9)

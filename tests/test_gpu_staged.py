@@ -85,6 +85,37 @@ def test_staged_variant_matches_oracle(cme, orc, n, kid):
     assert not st.any()
 
 
+def _staged_f32_params():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(n, k) for n in (8192, 16384, 32768, 65536)
+                for k in C.cme_list_kernels(C.CME_F32, n) if C.cme_kernel_info(k)["kind"] == 6]
+    except Exception:
+        return [(16384, 0)]
+
+
+@pytest.mark.parametrize("n,kid", _staged_f32_params())
+def test_staged_fp32_variant_matches_fp64_oracle(cme, orc, n, kid):
+    """FP32 state and transforms (FP64 stage arithmetic) against the FP64 oracle."""
+    import torch
+    batch, steps = {8192: (3, 3), 16384: (2, 3), 32768: (1, 2), 65536: (1, 2)}[n]
+    p = W.pack(moderate_batch(2100 + n, [n] * batch))
+    h = 0.01
+    with cme.Plan(p, h, precision=cme.CME_F32) as plan:
+        plan.select(n, kid)
+        A = plan.state(p.a0)
+        assert A.dtype == torch.complex64
+        plan.run(A, steps, step0=5)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy().astype(np.complex128)
+        assert not plan.status().any()
+        name = plan.kernel(n)["name"]
+    ref, _ = orc.run(p, h, steps, step0=5)
+    errs = [rel_err(y[p.slice(b)], ref[p.slice(b)]) for b in range(batch)]
+    print(f"N={n} {name}: {errs}", flush=True)
+    assert max(errs) <= 2e-6
+
+
 def test_staged_mixed_plan_matches_oracle(cme, orc):
     """Staged and LDS-resident classes in one plan (concurrent launches)."""
     sizes = [16384, 2048, 512, 16384, 8192]
