@@ -8,7 +8,8 @@ seeded generators of ``paper_1307_3428_amd.workloads``).
 What each call computes is documented in cme_oracle.c: the cyclic (or
 truncated) four-wave-mixing sum of Eq. (1)-(3) by O(N^2) correlations, the
 right-hand side of Eq. (1) in the rotating frame, classic RK4 (Sec. 2), its
-discrete adjoint, and the frequency-domain split-step map (Sec. 2).
+discrete adjoint, the frequency-domain split-step map (Sec. 2) and the
+interaction-picture RK4 with the exact integral of the detuning ramp.
 """
 from __future__ import annotations
 
