@@ -25,8 +25,9 @@
  *   - An instance is one resonator.  Its N mode amplitudes are stored
  *     contiguously in centred order: element i holds mode mu = i - N/2, so the
  *     pump mode mu = 0 is element N/2.  N must be a power of two,
- *     16 <= N <= 65536; above 8192 the cyclic sum only, in FP64 with any
- *     integrator or in FP32 with classic RK4 (CME_EUNSUPPORTED otherwise).
+ *     16 <= N <= 65536 (N <= 32768 with the padded sum); above 8192
+ *     transform points FP64 with any integrator (classic RK4 for the padded
+ *     sum) or FP32 with classic RK4 (CME_EUNSUPPORTED otherwise).
  *   - A batch packs instances back to back; instance b starts at element
  *     inst[b].mode_offset of every per-mode array (state, kappa, omega').
  *     Ranges of different instances must not overlap.  "total" below is the
@@ -74,7 +75,7 @@ enum {
   CME_FWM_PADDED = 1  /* FWM sum over the instance's own modes only (the literal
                          Kronecker delta of Eq. (2)), computed on 2N-point
                          transforms with the upper half held at zero; RK4,
-                         FP64, N = 128 ... 4096, no adjoint                  */
+                         FP64, N = 128 ... 32768, no adjoint                 */
 };
 
 /* Flags of cme_init (bitwise or). */
@@ -215,12 +216,13 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * staged through global memory, several workgroups per instance, with the
  * row length N1 in the V field, 7: interaction-picture RK4 on the
  * two-level transform, 8: interaction-picture RK4 on the staged
- * transforms, 9: split-step map on the staged transforms), instances per
- * workgroup,
+ * transforms, 9: split-step map on the staged transforms, 10: RK4 with
+ * the padded sum on the staged transforms), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
- * twiddles are held in registers; kinds 6, 8, 9: wavefronts per workgroup).
+ * twiddles are held in registers; kinds 6, 8, 9, 10: wavefronts per
+ * workgroup).
  * Returns 10, or CME_EINVAL. */
 int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 

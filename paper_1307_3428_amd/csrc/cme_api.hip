@@ -52,6 +52,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_staged_split(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_staged_pad(&n);
+    v.insert(v.end(), a, a + n);
     return v;
   }();
   *count = (int)all.size();
@@ -118,13 +120,13 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 const Variant *all_variants(int *count) { return cme::variants(count); }
 
-// kinds 4 and 9 step the split-step map, kind 5 RK4 with the padded sum,
+// kinds 4 and 9 step the split-step map, kinds 5 and 10 RK4 with the padded sum,
 // kinds 7 and 8 interaction-picture RK4, all others RK4 with the cyclic sum;
 // `integrator` encodes both choices as integrator + 16 fwm
 bool integrates(const Variant &v, int integrator) {
   const int fwm = integrator >> 4, integ = integrator & 15;
-  if (fwm == CME_FWM_PADDED) return v.kind == 5;
-  if (v.kind == 5) return false;
+  if (fwm == CME_FWM_PADDED) return v.kind == 5 || v.kind == 10;
+  if (v.kind == 5 || v.kind == 10) return false;
   if (v.kind == 4 || v.kind == 9) return integ == CME_SPLIT_STEP;
   if (v.kind == 7 || v.kind == 8) return integ == CME_RK4IP;
   return integ == CME_RK4;
@@ -395,12 +397,14 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   int64_t total = 0;
   int rc = validate_instances(batch, inst, &total);
   if (rc != CME_OK) return rc;
-  // transforms longer than 8192 points run only on the staged kernels: the
-  // cyclic sum, FP64 with any integrator or FP32 with classic RK4
-  for (int32_t b = 0; b < batch; ++b)
-    if ((fwm == CME_FWM_PADDED ? 2 : 1) * inst[b].n_modes > 8192 &&
-        (fwm != CME_FWM_CYCLIC || (precision != CME_F64 && integrator != CME_RK4)))
+  // transforms of up to 65536 points; longer than 8192 only on the staged
+  // kernels: FP64 with any integrator (classic RK4 for the padded sum) or
+  // FP32 with classic RK4
+  for (int32_t b = 0; b < batch; ++b) {
+    const int64_t tn = (fwm == CME_FWM_PADDED ? 2 : 1) * (int64_t)inst[b].n_modes;
+    if (tn > 65536 || (tn > 8192 && precision != CME_F64 && integrator != CME_RK4))
       return CME_EUNSUPPORTED;
+  }
 
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return CME_ENODEVICE;

@@ -108,7 +108,8 @@ struct Variant {
                    // (cme_staged.hip; `v` holds the row length N1), 7: interaction-
                    // picture RK4 (cme_rk4ip.hip), 8: interaction-picture RK4 on the
                    // staged transforms (cme_staged.hip), 9: split-step map on the
-                   // staged transforms (cme_staged.hip)
+                   // staged transforms (cme_staged.hip), 10: RK4 with the padded sum
+                   // on the staged transforms (cme_staged.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -129,6 +130,7 @@ const Variant *variants_staged(int *count);  // cme_staged.hip
 const Variant *variants_rk4ip(int *count);   // cme_rk4ip.hip
 const Variant *variants_staged_ip(int *count);  // cme_staged.hip (interaction picture)
 const Variant *variants_staged_split(int *count);  // cme_staged.hip (split-step)
+const Variant *variants_staged_pad(int *count);    // cme_staged.hip (padded sum)
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 // The four-wave-mixing sum alone for one size class (cme_fwm.hip): reads the

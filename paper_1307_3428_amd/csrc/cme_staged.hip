@@ -110,15 +110,24 @@ template <int N, int N1, int E, int WPB> struct RowShape {
 //   stage 2: k2 = N(u2), ACC += 2 k2, next yI + h/2 k2;
 //   stage 3: k3 = N(u3), ACC += 2 k3, next P2 (yI + h k3);
 //   stage 4: k4 = N(u4), y' = P2 (yI + h/6 ACC) + h/6 k4.
+// PAD: the alias-free truncated sum (CME_FWM_PADDED): the instance's N/2
+// modes sit at transform indices [N/4, 3N/4) (index i <-> mode i - N/4 of
+// the caller's state); the derivative is zero outside that band, so the
+// other half stays zero and the cyclic sum over the band is the literal one.
 // STAGE < 0: start the inverse transform of the state (first launch of a run);
 // STAGE = s in 0..3: RK4 stage s + 1 as described above; STAGE = 4: finish
 // the forward transform and write the four-wave-mixing sum K = (N K) / N
 // (cme_fwm), packed like the state, to a.ckpt.
-template <int N, int N1, int E, int WPB, int STAGE, bool IP = false, typename Real = double>
+template <int N, int N1, int E, int WPB, int STAGE, bool IP = false, typename Real = double,
+          bool PAD = false>
 __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
   using SH = ColShape<N, N1, E, WPB>;
   constexpr int N2 = SH::N2, T = SH::T;
   static_assert(!IP || std::is_same<Real, double>::value, "the interaction picture is FP64");
+  static_assert(!PAD || (!IP && STAGE < 4), "the padded sum steps classic RK4");
+  constexpr int Q4 = N / 4;
+  auto in_band = [](int i) { return !PAD || (i >= Q4 && i < 3 * Q4); };
+  auto phys = [](int i) { return PAD ? i - Q4 : i; };  // index in the caller's state
   __shared__ cx<Real> lds[WPB * SH::CW * SH::LB];
   const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
   const int slot = (int)blockIdx.x / SH::NB, cb = (int)blockIdx.x % SH::NB;
@@ -138,7 +147,8 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
   if constexpr (STAGE < 0) {
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      v[m] = A[m1 + N1 * (t + m * T)];
+      const int i = m1 + N1 * (t + m * T);
+      v[m] = in_band(i) ? A[phys(i)] : cx<Real>{(Real)0, (Real)0};
     });
   } else {
     // outer sum of the forward transform: v[m] = N K at mode m1 + N1 (t + m T)
@@ -206,13 +216,15 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const int i = m1 + N1 * (t + m * T);
-      const cx<double> y = up(A[i]);
+      const bool band = in_band(i);
+      const cx<double> y = band ? up(A[phys(i)]) : cx<double>{0.0, 0.0};
       const cx<double> u = STAGE == 0 ? y : up(U[i]);
       const cx<double> nk = up(v[m]);
       const double lr = -0.5 * kap[i], li = omg[i] - sig;
       // k = L u + i (g0/N) N K
       cx<double> k = {lr * u.re - li * u.im - d.g0n * nk.im, lr * u.im + li * u.re + d.g0n * nk.re};
       if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
+      if (!band) k = {0.0, 0.0};
       cx<double> nxt;
       if constexpr (STAGE == 0) {
         ACC[i] = dn<Real>(k);
@@ -228,8 +240,10 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
         const cx<double> acc = up(ACC[i]);
         const double c = h / 6.0;
         nxt = {y.re + c * (acc.re + k.re), y.im + c * (acc.im + k.im)};
-        A[i] = dn<Real>(nxt);
-        if (a.ckpt) a.ckpt[d.a_offset + i] = dn<Real>(nxt);
+        if (band) {
+          A[phys(i)] = dn<Real>(nxt);
+          if (a.ckpt) a.ckpt[d.a_offset + phys(i)] = dn<Real>(nxt);
+        }
         bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
       }
       v[m] = dn<Real>(nxt);
@@ -286,7 +300,7 @@ __global__ void __launch_bounds__(64 * WPB) staged_row(StagedArgsT<Real> a) {
   });
 }
 
-template <int N, int N1, int E, int WPB, bool IP = false, typename Real = double>
+template <int N, int N1, int E, int WPB, bool IP = false, typename Real = double, bool PAD = false>
 hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
@@ -306,7 +320,7 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
   const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
   cx<Real> *ck = reinterpret_cast<cx<Real> *>(r.ckpt);
   a.t0 = (double)r.step0 * r.h;
-  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1, IP, Real>), cgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1, IP, Real, PAD>), cgrid, blk, 0, st, a);
   int64_t slot = 0;
   for (int64_t n = 0; n < r.n_steps; ++n) {
     a.t0 = (double)(r.step0 + n) * r.h;
@@ -314,13 +328,13 @@ hipError_t launch_staged(const RunArgs &r, hipStream_t st) {
     if (ck && r.ckpt_every > 0 && (n + 1) % r.ckpt_every == 0) a.ckpt = ck + (slot++) * r.total;
     a.tail = n + 1 == r.n_steps;
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 0, IP, Real, PAD>), cgrid, blk, 0, st, a);
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 1, IP, Real, PAD>), cgrid, blk, 0, st, a);
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 2, IP, Real, PAD>), cgrid, blk, 0, st, a);
     hipLaunchKernelGGL((staged_row<N, N1, E, WPB, Real>), rgrid, blk, 0, st, a);
-    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3, IP, Real>), cgrid, blk, 0, st, a);
+    hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 3, IP, Real, PAD>), cgrid, blk, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -559,6 +573,20 @@ const Variant kStagedSplitVariants[] = {
     split_staged_variant<32768, 256, 8, 8>(), split_staged_variant<65536, 256, 8, 8>(),
 };
 
+// alias-free truncated sum on the same transforms (kind 10): transform
+// length N for instances of N/2 = 8192 ... 32768 modes
+template <int N, int N1, int E, int WPB> constexpr Variant staged_pad_variant() {
+  using CS = ColShape<N, N1, E, WPB>;
+  using RS = RowShape<N, N1, E, WPB>;
+  return Variant{0, N, E, N1, kPS, WPB, 10, 1, 64 * WPB,
+                 CS::LDS_BYTES > RS::LDS_BYTES ? CS::LDS_BYTES : RS::LDS_BYTES,
+                 &launch_staged<N, N1, E, WPB, false, double, true>, nullptr, 3};
+}
+const Variant kStagedPadVariants[] = {
+    staged_pad_variant<16384, 128, 8, 8>(), staged_pad_variant<32768, 256, 8, 8>(),
+    staged_pad_variant<65536, 256, 8, 8>(),
+};
+
 // interaction-picture RK4 on the same transforms (kind 8)
 const Variant kStagedIpVariants[] = {
     staged_variant<8192, 128, 8, 8, true>(),  staged_variant<16384, 128, 8, 8, true>(),
@@ -574,6 +602,11 @@ hipError_t launch_staged_fwm(int n, const RunArgs &r, hipStream_t st) {
     case 65536: return fwm_staged<65536, 256, 8, 8>(r, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+const Variant *variants_staged_pad(int *count) {
+  *count = (int)(sizeof(kStagedPadVariants) / sizeof(kStagedPadVariants[0]));
+  return kStagedPadVariants;
 }
 
 const Variant *variants_staged_split(int *count) {

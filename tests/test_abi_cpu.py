@@ -54,7 +54,7 @@ def test_kernel_table_covers_every_size():
             e = info["elems_per_thread"]
             assert e & (e - 1) == 0 and 2 <= e <= n
             assert info["threads"] <= 1024 and info["lds_bytes"] <= 160 * 1024
-            if info["kind"] in (6, 8, 9):
+            if info["kind"] in (6, 8, 9, 10):
                 # staged: rows of N1 and columns of N / N1 points, each a
                 # team of whole lanes inside one wavefront
                 n1 = info["sub_transforms"]
@@ -66,7 +66,7 @@ def test_kernel_table_covers_every_size():
                 assert (n // e) % 64 == 0
             seen.add(k)
         # above 8192 only the staged kernels
-        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8, 9) for k in ids)
+        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8, 9, 10) for k in ids)
         assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] == 6
                                 for k in C.cme_list_kernels(C.CME_F32, n))
     assert C.cme_list_kernels(C.CME_F64, 100) == []
@@ -151,8 +151,9 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
         kw["integrator"] = C.CME_SPLIT_STEP
         expect = C.CME_EUNSUPPORTED
     elif case in ("large_fp32", "large_padded"):
-        # above 8192 transform points: the cyclic sum, FP32 only with classic RK4
-        inst = _inst(n=16384 if case != "large_padded" else 8192)
+        # FP32 above 8192 transform points only with classic RK4; at most
+        # 65536 transform points (32768 modes with the padded sum)
+        inst = _inst(n=16384 if case != "large_padded" else 65536)
         kw.update({"large_fp32": {"precision": C.CME_F32, "integrator": C.CME_RK4IP},
                    "large_padded": {"fwm": C.CME_FWM_PADDED}}[case])
         expect = C.CME_EUNSUPPORTED
