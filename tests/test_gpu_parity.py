@@ -481,6 +481,32 @@ def test_split_step_fig1_ensemble(cme, orc):
     assert max(errs) <= 1e-10, errs
 
 
+@pytest.mark.parametrize("n,batch", [(2048, 4), (65536, 2)])
+def test_split_step_is_unitary_without_loss_and_pump(cme, n, batch):
+    """With kappa = 0 and no pump every part of the split-step map is
+    unitary (the linear half steps are phase factors, the Kerr step a
+    pointwise phase rotation, the transform pair orthogonal up to 1/N), so
+    sum |A|^2 is conserved to rounding over 1000 steps at full size."""
+    import torch
+    insts = moderate_batch(8000 + n, [n] * batch)
+    for inst in insts:
+        inst.kappa[:] = 0.0
+        inst.a_in = 0j
+    p = W.pack(insts)
+    with cme.Plan(p, 1e-3, integrator=cme.CME_SPLIT_STEP) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, 1000)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        name = plan.kernel(n)["name"]
+    for b in range(batch):
+        p0 = np.sum(np.abs(p.a0[p.slice(b)]) ** 2)
+        p1 = np.sum(np.abs(y[p.slice(b)]) ** 2)
+        moved = rel_err(p.a0[p.slice(b)], y[p.slice(b)])
+        print(f"{name} instance {b}: power drift {abs(p1 - p0) / p0:.2e} (state moved {moved:.2e})")
+        assert abs(p1 - p0) <= 1e-11 * p0 and moved > 0.1
+
+
 def test_split_step_checkpoints_and_split_runs(cme):
     import torch
     p = W.pack(moderate_batch(13, [256, 2048, 128, 16384]))

@@ -565,3 +565,22 @@ def test_split_step_kerr_only_is_exact(orc):
     a = np.fft.ifft(inst.a0) * n
     ref = np.fft.fft(a * np.exp(1j * inst.g0 * np.abs(a) ** 2 * T)) / n
     assert np.max(np.abs(y - ref)) <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Property-based: the oracle's sums against the literal enumeration on
+# random sizes and states (hypothesis draws them; seeds are reproducible).
+# ---------------------------------------------------------------------------
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None, derandomize=True)
+@given(n=st.integers(min_value=1, max_value=11), seed=st.integers(min_value=0, max_value=2 ** 31),
+       scale=st.floats(min_value=1e-3, max_value=1e3))
+def test_fwm_property_literal_sum(orc, n, seed, scale):
+    rng = np.random.default_rng(seed)
+    a = crandn(rng, n, scale)
+    for cyclic in (True, False):
+        ref = brute_fwm(a, cyclic=cyclic)
+        got = orc.fwm(a, truncated=not cyclic)
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(a).max() ** 3 * n * n)
