@@ -170,7 +170,10 @@ int cme_fwm(cme_plan *plan, const void *A, void *K);
  * ckpt: device complex [n_steps / ckpt_every][total] as written by cme_run
  * with the same step0 / ckpt_every, or NULL (the adjoint then runs the
  * forward pass itself).  A0 is not modified.  Uses plan-owned device scratch
- * of 8 * ckpt_every * total complex values (allocated on first use).  FP64
+ * of 8 * ckpt_every * total complex values per record buffer, two when the
+ * run has more than one segment (allocated on first use), and a plan-owned
+ * stream on which each segment's recompute runs beside the reverse sweep of
+ * the segment after it; the call stays ordered on the plan's stream.  FP64
  * RK4 with the cyclic sum and N <= 8192 only (CME_EUNSUPPORTED otherwise); a
  * size running the staged variant recomputes and reverses with a variant of
  * the same size that has a reverse sweep. */

@@ -107,6 +107,14 @@ struct cme_plan {
   size_t state_bytes = 0;
   void *d_gA = nullptr;
   size_t gA_bytes = 0;
+  // the adjoint's second stage-record buffer, and the stream and events that
+  // let a segment's recompute run beside the previous segment's reverse sweep
+  void *d_stages2 = nullptr;
+  size_t stages2_bytes = 0;
+  hipStream_t adj_stream = nullptr;
+  hipEvent_t adj_entry = nullptr;
+  hipEvent_t rec_done[2] = {nullptr, nullptr};
+  hipEvent_t rev_done[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -236,8 +244,12 @@ void free_plan(cme_plan *p) {
     if (c.side) (void)hipStreamDestroy(c.side);
   }
   if (p->fork) (void)hipEventDestroy(p->fork);
+  hipEvent_t evs[] = {p->adj_entry, p->rec_done[0], p->rec_done[1], p->rev_done[0], p->rev_done[1]};
+  for (hipEvent_t e : evs)
+    if (e) (void)hipEventDestroy(e);
+  if (p->adj_stream) (void)hipStreamDestroy(p->adj_stream);
   void *bufs[] = {p->d_inst, p->d_kappa, p->d_omega, p->d_flags, p->d_stages,
-                  p->d_ckpt, p->d_state, p->d_gA};
+                  p->d_ckpt, p->d_state, p->d_gA, p->d_stages2};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(cur);
@@ -271,20 +283,36 @@ cme::RunArgs run_args(const cme_plan *p, const SizeClass &c, void *A, int64_t st
 // on the caller's stream and are joined back into it: the classes share the
 // chip, and the call stays ordered on the caller's stream (and capturable
 // into a graph, where it becomes parallel branches).
+// (on `base`, the plan's stream unless the adjoint's own stream is given)
 int launch_forward(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
-                   void *ckpt, void *stages) {
+                   void *ckpt, void *stages, hipStream_t base) {
   const size_t nc = p->classes.size();
-  if (nc > 1) HIP_TRY(hipEventRecord(p->fork, p->stream));
+  if (nc > 1) HIP_TRY(hipEventRecord(p->fork, base));
   for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
   for (size_t i = 0; i < nc; ++i) {
     SizeClass &c = p->classes[i];
     const cme::RunArgs a = run_args(p, c, A, step0, n_steps, ckpt_every, ckpt, stages);
-    if (c.var->fwd(a, i == 0 ? p->stream : c.side) != hipSuccess) return CME_EHIP;
+    if (c.var->fwd(a, i == 0 ? base : c.side) != hipSuccess) return CME_EHIP;
   }
   for (size_t i = 1; i < nc; ++i) {
     HIP_TRY(hipEventRecord(p->classes[i].done, p->classes[i].side));
-    HIP_TRY(hipStreamWaitEvent(p->stream, p->classes[i].done, 0));
+    HIP_TRY(hipStreamWaitEvent(base, p->classes[i].done, 0));
   }
+  return CME_OK;
+}
+
+int launch_forward(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
+                   void *ckpt, void *stages) {
+  return launch_forward(p, A, step0, n_steps, ckpt_every, ckpt, stages, p->stream);
+}
+
+// the adjoint's stream and events, created on first use (default priority)
+int adjoint_streams(cme_plan *p) {
+  if (p->adj_stream) return CME_OK;
+  HIP_TRY(hipStreamCreateWithFlags(&p->adj_stream, hipStreamNonBlocking));
+  hipEvent_t *evs[] = {&p->adj_entry, &p->rec_done[0], &p->rec_done[1], &p->rev_done[0],
+                       &p->rev_done[1]};
+  for (hipEvent_t *e : evs) HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
   return CME_OK;
 }
 
@@ -606,10 +634,13 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
   const int64_t nseg = (n_steps + K - 1) / K;
   int rc = grow(&p->d_stages, &p->stages_bytes, vec * 8 * (size_t)K);
   if (rc != CME_OK) return rc;
+  if (nseg > 1 && (rc = grow(&p->d_stages2, &p->stages2_bytes, vec * 8 * (size_t)K)) != CME_OK)
+    return rc;
   rc = grow(&p->d_state, &p->state_bytes, vec);
   if (rc != CME_OK) return rc;
   rc = grow(&p->d_gA, &p->gA_bytes, vec);
   if (rc != CME_OK) return rc;
+  if ((rc = adjoint_streams(p)) != CME_OK) return rc;
   const unsigned char *ck = (const unsigned char *)ckpt;
   if (!ck && nseg > 1) {
     // no checkpoints given: run the forward pass once, keeping segment starts
@@ -621,20 +652,42 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
     ck = (const unsigned char *)p->d_ckpt;
   }
   HIP_TRY(hipMemcpyAsync(p->d_gA, gA_T, vec, hipMemcpyDefault, p->stream));
-  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+  // The segment recomputes run on the adjoint's stream, the reverse sweeps on
+  // the plan's stream: the recompute of segment s - 1 needs only its
+  // checkpoint, so it runs beside the reverse sweep of segment s (two record
+  // buffers, used by alternate segments).  Events order each buffer's reuse
+  // and join every recompute back into the plan's stream.
+  void *bufs[2] = {p->d_stages, nseg > 1 ? p->d_stages2 : p->d_stages};
+  HIP_TRY(hipEventRecord(p->adj_entry, p->stream));
+  HIP_TRY(hipStreamWaitEvent(p->adj_stream, p->adj_entry, 0));
+  auto recompute = [&](int64_t seg) -> int {
+    const int b = (int)(seg & 1);
     const int64_t first = seg * K;
     const int64_t len = std::min<int64_t>(K, n_steps - first);
+    // the reverse sweep of segment seg + 2 read this buffer last
+    if (seg + 2 < nseg) HIP_TRY(hipStreamWaitEvent(p->adj_stream, p->rev_done[b], 0));
     const void *start = seg == 0 ? A0 : (const void *)(ck + (size_t)(seg - 1) * vec);
-    HIP_TRY(hipMemcpyAsync(p->d_state, start, vec, hipMemcpyDefault, p->stream));
-    rc = launch_forward(p, p->d_state, step0 + first, len, 0, nullptr, p->d_stages);
-    if (rc != CME_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(p->d_state, start, vec, hipMemcpyDefault, p->adj_stream));
+    const int r = launch_forward(p, p->d_state, step0 + first, len, 0, nullptr, bufs[b],
+                                 p->adj_stream);
+    if (r != CME_OK) return r;
+    HIP_TRY(hipEventRecord(p->rec_done[b], p->adj_stream));
+    return CME_OK;
+  };
+  if ((rc = recompute(nseg - 1)) != CME_OK) return rc;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int b = (int)(seg & 1);
+    const int64_t first = seg * K;
+    const int64_t len = std::min<int64_t>(K, n_steps - first);
+    if (seg >= 1 && (rc = recompute(seg - 1)) != CME_OK) return rc;
+    HIP_TRY(hipStreamWaitEvent(p->stream, p->rec_done[b], 0));
     for (auto &c : p->classes) {
       cme::AdjArgs a{};
       a.inst = p->d_inst;
       a.order = c.d_order;
       a.count = (int32_t)c.ids.size();
       a.n_seg = (int32_t)len;
-      a.stages = p->d_stages;
+      a.stages = bufs[b];
       a.gA = p->d_gA;
       a.kappa = p->d_kappa;
       a.omega = p->d_omega;
@@ -647,6 +700,7 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
       a.g_ain = g_ain;
       if (c.var->adj(a, p->stream) != hipSuccess) return CME_EHIP;
     }
+    HIP_TRY(hipEventRecord(p->rev_done[b], p->stream));
   }
   if (gA_0) HIP_TRY(hipMemcpyAsync(gA_0, p->d_gA, vec, hipMemcpyDefault, p->stream));
   return CME_OK;

@@ -284,6 +284,42 @@ def test_adjoint_matches_oracle(cme, orc):
     assert rel_err(gain[:, 0] + 1j * gain[:, 1], ref["g_ain"]) <= 1e-11
 
 
+def test_adjoint_segmentations_agree(cme, orc):
+    """Segment recomputes run beside the reverse sweeps in two alternating
+    record buffers: 1, 10 and 15 segments (with and without caller
+    checkpoints) agree to rounding (the checkpoints come from the plain
+    forward kernel, the records from its recording instantiation), a
+    repeated 15-segment call is bit for bit the same, and the 15-segment
+    result matches the oracle."""
+    import torch
+    p = W.pack(moderate_batch(9, [2048, 1024]))
+    h, steps = 2e-3, 100
+    rng = np.random.default_rng(9)
+    yT, _ = orc.run(p, h, steps)
+    gT = 4 * (np.abs(yT) ** 2 - rng.uniform(0, 0.01, p.total)) * yT
+    outs = {}
+    with cme.Plan(p, h) as plan:
+        A0 = plan.state(p.a0)
+        for K, with_ckpt in ((100, False), (10, True), (7, False), ("7 again", False)):
+            k = 7 if K == "7 again" else K
+            ck = None
+            if with_ckpt:
+                ck = torch.zeros((steps // k, p.total), dtype=A0.dtype, device=A0.device)
+                plan.run(A0.clone(), steps, ckpt_every=k, ckpt=ck)
+            g = plan.adjoint(A0, plan.state(gT), steps, ckpt_every=k, ckpt=ck)
+            torch.cuda.synchronize()
+            outs[K] = {key: v.cpu().numpy() for key, v in g.items()}
+    for key in ("gA_0", "g_omega", "g_kappa", "g_ain"):
+        assert np.array_equal(outs[7][key], outs["7 again"][key]), key
+        for K in (10, 7):
+            err = rel_err(outs[K][key], outs[100][key])
+            print(f"K={K} {key}: {err:.2e}")
+            assert err <= 1e-12, (K, key)
+    ref = orc.adjoint(p, h, steps, gT)
+    assert rel_err(outs[7]["gA_0"], ref["gy0"]) <= 1e-11
+    assert rel_err(outs[7]["g_omega"], ref["g_omega"]) <= 1e-11
+
+
 # ---------------------------------------------------------------------------
 # FP32 path: FP32 transforms and state, FP64 time / detuning bookkeeping.
 # Bar: relative L2 error <= 1e-4 against the FP64 oracle.
