@@ -103,6 +103,8 @@ def main() -> int:
     ap.add_argument("--kernel", type=int, default=-1, help="force a kernel variant id")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the adjoint leg (profiling) and exit")
     ap.add_argument("--staged-case", type=int, default=0, metavar="N",
                     help="only run the staged kernel on the staged leg's batch of size N "
                          "(8192, 16384 or 65536) for --rk-steps steps (profiling) and exit")
@@ -134,6 +136,10 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n * 8}))
+        return 0
+
+    if args.adjoint_only:
+        print(json.dumps(adjoint_leg(C, W, torch)))
         return 0
 
     if args.staged_case:
