@@ -111,6 +111,8 @@ struct cme_plan {
   // let a segment's recompute run beside the previous segment's reverse sweep
   void *d_stages2 = nullptr;
   size_t stages2_bytes = 0;
+  void *d_kbar = nullptr;   // kbar_s of a segment for the parameter cotangents
+  size_t kbar_bytes = 0;
   hipStream_t adj_stream = nullptr;
   hipEvent_t adj_entry = nullptr;
   hipEvent_t rec_done[2] = {nullptr, nullptr};
@@ -249,7 +251,7 @@ void free_plan(cme_plan *p) {
     if (e) (void)hipEventDestroy(e);
   if (p->adj_stream) (void)hipStreamDestroy(p->adj_stream);
   void *bufs[] = {p->d_inst, p->d_kappa, p->d_omega, p->d_flags, p->d_stages,
-                  p->d_ckpt, p->d_state, p->d_gA, p->d_stages2};
+                  p->d_ckpt, p->d_state, p->d_gA, p->d_stages2, p->d_kbar};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   (void)hipSetDevice(cur);
@@ -640,6 +642,9 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
   if (rc != CME_OK) return rc;
   rc = grow(&p->d_gA, &p->gA_bytes, vec);
   if (rc != CME_OK) return rc;
+  bool kbar = false;
+  for (auto &c : p->classes) kbar |= c.var->adj_kbar != 0;
+  if (kbar && (rc = grow(&p->d_kbar, &p->kbar_bytes, vec * 4 * (size_t)K)) != CME_OK) return rc;
   if ((rc = adjoint_streams(p)) != CME_OK) return rc;
   const unsigned char *ck = (const unsigned char *)ckpt;
   if (!ck && nseg > 1) {
@@ -698,7 +703,10 @@ int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, in
       a.g_omega = g_omega;
       a.g_kappa = g_kappa;
       a.g_ain = g_ain;
+      a.kbar = c.var->adj_kbar ? p->d_kbar : nullptr;
       if (c.var->adj(a, p->stream) != hipSuccess) return CME_EHIP;
+      if (c.var->adj_kbar && cme::launch_adj_params(c.n, a, p->stream) != hipSuccess)
+        return CME_EHIP;
     }
     HIP_TRY(hipEventRecord(p->rev_done[b], p->stream));
   }

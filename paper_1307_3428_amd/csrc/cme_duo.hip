@@ -538,8 +538,10 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
 // round A to round C).
 // Parameter cotangents per stage: gbar_omega += Re(conj(kbar) i u),
 // gbar_kappa -= Re(conj(kbar) u) / 2, gbar_Ain += sqrt(kappa_ext) kbar at
-// mu = 0.  The stage records (u_s in mode order, a_s in the time-domain
-// slot order) are loaded a round before they are needed.
+// mu = 0.  This kernel only stores kbar_s (a.kbar); adj_params forms the
+// sums from it and the stage inputs u_s afterwards, so neither the
+// accumulators nor u_s occupy registers here.  The time-domain records a_s
+// are loaded a round before they are needed.
 template <typename Real, int N, int E, int PS, int NV, int FT>
 __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_reverse(AdjArgs a) {
   using SH = DuoShape<Real, N, E, PS>;
@@ -562,7 +564,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> yb1[E], yb[E], k2[E], va[E], vb[E], ra[E], rb[E];
-  Real lr[E], gom[E], gka[E];
+  Real lr[E];
   double om[E];
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
@@ -570,11 +572,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     yb1[m] = gA[i];
     lr[m] = (Real)(-0.5 * kap[i]);
     om[m] = omg[i];
-    gom[m] = (Real)0;
-    gka[m] = (Real)0;
   });
-  const bool pump_owner = (w == 0 && lane == 0);
-  cx<Real> gain = {(Real)0, (Real)0};
+  cx<Real> *kbar = reinterpret_cast<cx<Real> *>(a.kbar);
   const Real gn = (Real)d.g0n, nn_r = (Real)N;
   const double h = a.h;
   const Real hw1 = (Real)(h / 6.0), hw2 = (Real)(h / 3.0), hh = (Real)(0.5 * h), hf = (Real)h;
@@ -594,13 +593,10 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     return cx<Real>{p2 * z.re + a2.re * z.re + a2.im * z.im,
                     p2 * z.im + a2.im * z.re - a2.re * z.im};
   };
-  auto grads = [&](auto mi, const cx<Real> &kv, const cx<Real> &u) {
+  // kbar_s of step n, for the parameter cotangents (launch_adj_params)
+  auto store_kbar = [&](int64_t n, int s, auto mi, const cx<Real> &kv) {
     constexpr int m = decltype(mi)::value;
-    gom[m] += kv.im * u.re - kv.re * u.im;
-    gka[m] -= (Real)0.5 * (kv.re * u.re + kv.im * u.im);
-    if constexpr (m == E / 2) {
-      if (pump_owner) gain = cadd(gain, kv);
-    }
+    kbar[(n * 4 + s) * a.total + d.offset + WP::mode(w, lane, m)] = kv;
   };
   // record addresses are rebuilt at each use (an opaque base) rather than
   // kept in registers for the whole run
@@ -611,15 +607,6 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       dst[m] = rec[base + (WP::tslot(w, lane, m) - WP::tslot(w, lane, 0))];
-    });
-  };
-  auto load_u = [&](cx<Real> (&dst)[E], int64_t n, int s) {
-    const cx<Real> *rec = stages + stage_offset(n, s, a.total) + d.offset;
-    int base = WP::mode(w, lane, 0);
-    asm volatile("" : "+v"(base));
-    sfor<0, E>([&](auto mi) {
-      constexpr int m = decltype(mi)::value;
-      dst[m] = rec[base + (WP::mode(w, lane, m) - WP::mode(w, lane, 0))];
     });
   };
 
@@ -646,19 +633,17 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       vb[m] = kerr_t(mig(x3), rb[m]);
     });
     // ---- B: DFT(q_4), DFT(q_3)
-    load_u(ra, nn, 3);
-    load_u(rb, nn, 2);
     lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> k4 = {hw1 * yb1[m].re, hw1 * yb1[m].im};
       const cx<Real> c4 = clin(k4, mi, s4);
       const cx<Real> ub4 = {c4.re + va[m].re, c4.im + va[m].im};
-      grads(mi, k4, ra[m]);
+      store_kbar(nn, 3, mi, k4);
       const cx<Real> k3 = {hw2 * yb1[m].re + hf * ub4.re, hw2 * yb1[m].im + hf * ub4.im};
       const cx<Real> c3 = clin(k3, mi, s2);
       const cx<Real> ub3 = {c3.re + vb[m].re, c3.im + vb[m].im};
-      grads(mi, k3, rb[m]);
+      store_kbar(nn, 2, mi, k3);
       yb[m] = {yb1[m].re + ub4.re + ub3.re, yb1[m].im + ub4.im + ub3.im};
       k2[m] = {hw2 * yb1[m].re + hh * ub3.re, hw2 * yb1[m].im + hh * ub3.im};
       const cx<Real> c2 = clin(k2[m], mi, s2);
@@ -678,18 +663,16 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       vb[m] = kerr_t(mig(x1), rb[m]);
     });
     // ---- D: DFT(q_2), DFT(q_1)
-    load_u(ra, nn, 1);
-    load_u(rb, nn, 0);
     lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> c2 = clin(k2[m], mi, s2);
       const cx<Real> ub2 = {c2.re + va[m].re, c2.im + va[m].im};
-      grads(mi, k2[m], ra[m]);
+      store_kbar(nn, 1, mi, k2[m]);
       const cx<Real> k1 = {hw1 * yb1[m].re + hh * ub2.re, hw1 * yb1[m].im + hh * ub2.im};
       const cx<Real> c1 = clin(k1, mi, s1);
       const cx<Real> ub1 = {c1.re + vb[m].re, c1.im + vb[m].im};
-      grads(mi, k1, rb[m]);
+      store_kbar(nn, 0, mi, k1);
       yb1[m] = {yb[m].re + ub2.re + ub1.re, yb[m].im + ub2.im + ub1.im};
     });
   }
@@ -697,13 +680,43 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     constexpr int m = decltype(mi)::value;
     const int i = WP::mode(w, lane, m);
     gA[i] = yb1[m];
-    if (a.g_omega) a.g_omega[d.offset + i] += (double)gom[m];
-    if (a.g_kappa) a.g_kappa[d.offset + i] += (double)gka[m];
   });
-  if (pump_owner && a.g_ain) {
-    a.g_ain[2 * id] += d.sqrt_kext * (double)gain.re;
-    a.g_ain[2 * id + 1] += d.sqrt_kext * (double)gain.im;
+}
+
+// Parameter cotangents of one segment from the stage inputs u_s and the
+// kbar_s the paired reverse sweep stored: one thread per mode, summing over
+// the segment's steps and stages (FP64).
+__global__ void __launch_bounds__(256) adj_params(AdjArgs a, int n) {
+  const int nb = (n + 255) / 256;
+  const int slot = (int)blockIdx.x / nb, i = ((int)blockIdx.x % nb) * 256 + (int)threadIdx.x;
+  if (slot >= a.count || i >= n) return;
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  const cx<double> *st = reinterpret_cast<const cx<double> *>(a.stages);
+  const cx<double> *kb = reinterpret_cast<const cx<double> *>(a.kbar);
+  double go = 0.0, gk = 0.0;
+  cx<double> gain = {0.0, 0.0};
+  for (int nn = 0; nn < a.n_seg; ++nn) {
+    for (int s = 0; s < 4; ++s) {
+      const cx<double> u = st[stage_offset(nn, s, a.total) + d.offset + i];
+      const cx<double> kv = kb[((int64_t)nn * 4 + s) * a.total + d.offset + i];
+      go += kv.im * u.re - kv.re * u.im;
+      gk -= 0.5 * (kv.re * u.re + kv.im * u.im);
+      if (i == n / 2) gain = cadd(gain, kv);
+    }
   }
+  if (a.g_omega) a.g_omega[d.offset + i] += go;
+  if (a.g_kappa) a.g_kappa[d.offset + i] += gk;
+  if (i == n / 2 && a.g_ain) {
+    a.g_ain[2 * id] += d.sqrt_kext * gain.re;
+    a.g_ain[2 * id + 1] += d.sqrt_kext * gain.im;
+  }
+}
+
+hipError_t launch_adj_params(int n, const AdjArgs &a, hipStream_t st) {
+  const int nb = (n + 255) / 256;
+  hipLaunchKernelGGL(adj_params, dim3(a.count * nb), dim3(256), 0, st, a, n);
+  return hipGetLastError();
 }
 
 template <typename Real, int N, int E, int PS, int NV, int FT>
@@ -750,7 +763,8 @@ template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant
   using SH = DuoShape<Real, N, E, PS>;
   if constexpr (std::is_same<Real, double>::value)
     return Variant{0, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
-                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, duo_adj_ptr<Real, N, E, PS, NV>()};
+                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, duo_adj_ptr<Real, N, E, PS, NV>(), 0,
+                   N / (64 * E) < 8 ? 1 : 0};
   else  // FP32 plans have no adjoint
     return Variant{1, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
                    &launch_duo_fwd<Real, N, E, PS, NV, FT>, nullptr};

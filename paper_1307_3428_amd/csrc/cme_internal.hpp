@@ -59,6 +59,9 @@ struct AdjArgs {
   double *g_omega;         // [total] or null (accumulated)
   double *g_kappa;         // [total] or null (accumulated)
   double *g_ain;           // [2 batch] or null (accumulated)
+  void *kbar;              // variants with adj_kbar: the reverse sweep stores kbar_s of every
+                           // step and stage here, [K][4][total] complex, in place of
+                           // accumulating the parameter cotangents (launch_adj_params does)
 };
 
 // Offset of the stage-s record of step n in the adjoint stage buffer: the
@@ -116,6 +119,7 @@ struct Variant {
   FwdLaunch fwd;
   AdjLaunch adj;   // null if no adjoint kernel for this variant (FP32)
   int work = 0;    // complex values of class workspace per mode (RunArgs::work)
+  int adj_kbar = 0;  // the reverse sweep stores kbar_s (AdjArgs::kbar) for launch_adj_params
 };
 
 const Variant *variants_team(int *count);  // cme_kernels.hip
@@ -137,5 +141,12 @@ const Variant *variants(int *count);       // all of them (cme_api.hip)
 // packed amplitudes at a.A and writes K at a.ckpt (same packing); sizes above
 // 8192 use the staged transform and the class workspace a.work.
 hipError_t launch_fwm(int precision, int n, const RunArgs &a, hipStream_t st);
+
+// Parameter cotangents of one segment from the stage inputs u_s (a.stages)
+// and the stored kbar_s (a.kbar) of a class of n-mode instances (FP64,
+// cme_duo.hip): g_omega += Re(conj(kbar) i u), g_kappa -= Re(conj(kbar) u) / 2,
+// g_ain += sqrt(kappa_ext) kbar at mu = 0, summed over the segment's steps and
+// stages.
+hipError_t launch_adj_params(int n, const AdjArgs &a, hipStream_t st);
 
 }  // namespace cme
