@@ -747,16 +747,16 @@ hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
 // NV: VALU instructions scheduled after each LDS instruction of the other
 // sequence (reported as the variant's exchange field)
 // FT: twiddles formed from one base per pass (0) or all powers held in
-// registers (1); reported as exchange = NV + 16 FT.  The reverse sweep has
-// more live state and always forms its twiddles (it reads the stage records
-// in the same slot order whatever the forward kernel's twiddle source).
+// registers (1); reported as exchange = NV + 16 FT.  The reverse sweep holds
+// all powers in registers too (it reads the stage records in the same slot
+// order whatever the forward kernel's twiddle source).
 // Reverse sweep of a paired forward kernel: the paired reverse, except at
 // eight wavefronts per instance (N = 4096), where its registers do not fit
 // two waves per SIMD and the lean reverse, which reads the same stage
 // records, is used.
 template <typename Real, int N, int E, int PS, int NV> constexpr AdjLaunch duo_adj_ptr() {
   if constexpr (N / (64 * E) >= 8) return &launch_lean_adj<Real, N, E, PS>;
-  else return &launch_duo_adj<Real, N, E, PS, NV, 0>;
+  else return &launch_duo_adj<Real, N, E, PS, NV, 1>;
 }
 
 template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant duo_variant() {
