@@ -25,11 +25,11 @@
 
 namespace cme {
 
-template <typename Real, int N, int E, int PS> struct SplitShape {
+template <typename Real, int N, int E, int PS, int IPB_ = 0> struct SplitShape {
   using LP = LeanPlan<N, E>;
   static constexpr int W = LP::W;
   static constexpr int WV = LP::WV;
-  static constexpr int IPB = W == 1 ? 4 : 1;
+  static constexpr int IPB = IPB_ > 0 ? IPB_ : (W == 1 ? 4 : 1);
   static constexpr int LB1 = LdsLen<LP::N1, PS>::value;
   static constexpr int LIMIT = 160 * 1024;
   static constexpr int ONE = IPB * WV * LB1 * (int)sizeof(cx<Real>);
@@ -40,9 +40,9 @@ template <typename Real, int N, int E, int PS> struct SplitShape {
   static_assert(LDS_BYTES <= LIMIT, "LDS over the gfx950 per-workgroup limit");
 };
 
-template <typename Real, int N, int E, int PS>
-__global__ void __launch_bounds__((SplitShape<Real, N, E, PS>::THREADS)) split_lean(RunArgs a) {
-  using SH = SplitShape<Real, N, E, PS>;
+template <typename Real, int N, int E, int PS, int IPB_ = 0>
+__global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) split_lean(RunArgs a) {
+  using SH = SplitShape<Real, N, E, PS, IPB_>;
   using WP = WavePlan<N, E, 1, 0>;
   constexpr int W = WP::W;
   static_assert(std::is_same<Real, double>::value, "the split-step kernels are FP64");
@@ -152,25 +152,29 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS>::THREADS)) split_l
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int PS>
+template <typename Real, int N, int E, int PS, int IPB_ = 0>
 hipError_t launch_split(const RunArgs &a, hipStream_t st) {
-  using SH = SplitShape<Real, N, E, PS>;
+  using SH = SplitShape<Real, N, E, PS, IPB_>;
   const int grid = (a.count + SH::IPB - 1) / SH::IPB;
-  hipLaunchKernelGGL((split_lean<Real, N, E, PS>), dim3(grid), dim3(SH::THREADS), 0, st, a);
+  hipLaunchKernelGGL((split_lean<Real, N, E, PS, IPB_>), dim3(grid), dim3(SH::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
-template <typename Real, int N, int E, int PS> constexpr Variant split_variant() {
-  using SH = SplitShape<Real, N, E, PS>;
+template <typename Real, int N, int E, int PS, int IPB_ = 0> constexpr Variant split_variant() {
+  using SH = SplitShape<Real, N, E, PS, IPB_>;
   return Variant{0, N, E, 1, PS, 0, 4, SH::IPB, SH::THREADS, SH::LDS_BYTES,
-                 &launch_split<Real, N, E, PS>, nullptr};
+                 &launch_split<Real, N, E, PS, IPB_>, nullptr};
 }
 
-// (N, E, PS): one wavefront per instance up to N = 512, then E = 8
+// (N, E, PS[, instances per workgroup]): one wavefront per instance up to
+// N = 256, then E = 8.  Single-wavefront instances run one per workgroup by
+// default (each on its own CU when the batch is small: the paper's Fig. 1
+// set steps 10% faster than with four per workgroup) or four per workgroup.
 static const Variant kSplitVariants[] = {
-    split_variant<double, 128, 2, 1>(),  split_variant<double, 256, 4, 2>(),
-    split_variant<double, 512, 8, 3>(),  split_variant<double, 1024, 8, 3>(),
-    split_variant<double, 2048, 8, 3>(), split_variant<double, 4096, 8, 3>(),
+    split_variant<double, 128, 2, 1, 1>(), split_variant<double, 256, 4, 2, 1>(),
+    split_variant<double, 128, 2, 1>(),    split_variant<double, 256, 4, 2>(),
+    split_variant<double, 512, 8, 3>(),    split_variant<double, 1024, 8, 3>(),
+    split_variant<double, 2048, 8, 3>(),   split_variant<double, 4096, 8, 3>(),
 };
 
 const Variant *variants_split(int *count) {
