@@ -112,6 +112,23 @@ def test_oracle_split_step_is_the_lle_split_step(orc, n, steps, h):
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("n,steps,h", [(16, 200, 5e-3), (64, 150, 5e-3)])
+def test_oracle_rk4ip_is_the_lle_rk4ip(orc, n, steps, h):
+    """The interaction-picture RK4 in mode space (the oracle) and in the time
+    domain (matrix exponential of the differential operator) are the same
+    map: psi = T A carries one into the other."""
+    rng = np.random.default_rng(250 + n)
+    res = L.random_resonator(rng, n)
+    psi0 = start_state(rng, res)
+    p = W.pack([as_instance(res, psi0)])
+    y_orc = orc.rk4ip_run(p, h, steps)
+    y_lle = L.to_modes(res.rk4ip(psi0, h, steps))
+    err = rel_err(y_orc, y_lle)
+    moved = rel_err(p.a0, y_lle)
+    print(f"N={n}: oracle RK4IP vs LLE RK4IP {err:.2e} (moved {moved:.2e})")
+    assert err <= 1e-12 and moved > 1e-2
+
+
 def test_nonuniform_loss_is_not_a_scalar_lle(orc):
     """Negative control: with quadratic loss the LLE needs the diffusive
     operator; dropping it (a scalar-loss LLE) leaves a visible difference."""
@@ -168,6 +185,22 @@ def test_gpu_rk4_is_the_lle_rk4(cme, n, steps):
         ref = L.to_modes(r.rk4(s, h, steps))
         err = rel_err(y[p.slice(b)], ref)
         print(f"N={n} {names[n]} resonator {b}: GPU vs LLE {err:.2e}", flush=True)
+        assert err <= 1e-11
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,steps", [(128, 200), (1024, 100)])
+def test_gpu_rk4ip_is_the_lle_rk4ip(cme, n, steps):
+    h = 5e-3
+    rng = np.random.default_rng(450 + n)
+    ress = [L.random_resonator(rng, n) for _ in range(2)]
+    psis = [start_state(rng, r) for r in ress]
+    p = W.pack([as_instance(r, s) for r, s in zip(ress, psis)])
+    y, names = gpu_run(cme, p, h, steps, integrator=cme.CME_RK4IP)
+    for b, (r, s) in enumerate(zip(ress, psis)):
+        ref = L.to_modes(r.rk4ip(s, h, steps))
+        err = rel_err(y[p.slice(b)], ref)
+        print(f"N={n} {names[n]} resonator {b}: GPU RK4IP vs LLE RK4IP {err:.2e}", flush=True)
         assert err <= 1e-11
 
 
