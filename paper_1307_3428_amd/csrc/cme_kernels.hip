@@ -41,6 +41,9 @@ template <typename Real, int N, int E, int PS> struct KernelShape {
   static constexpr int NBUF = PING ? 2 : 1;
   static constexpr int LDS_BYTES = IPB * NBUF * LB * (int)sizeof(cx<Real>);
   static constexpr int THREADS = IPB * T;
+  // a workgroup of one wavefront orders its LDS exchanges without a
+  // workgroup barrier (one wavefront's LDS operations execute in order)
+  static constexpr int SYNC = THREADS <= 64 ? SYNC_WAVE : SYNC_BLOCK;
   static_assert(LDS_BYTES <= LDS_LIMIT, "LDS over the gfx950 per-workgroup limit");
   static_assert(THREADS <= 1024, "workgroup too large");
 };
@@ -104,13 +107,13 @@ __global__ void __launch_bounds__((KernelShape<Real, N, E, PS>::THREADS))
         cx<Real> *st = stages + stage_offset(n, s, a.total) + d.offset;
         sfor<0, E>([&](auto mi) { st[t + decltype(mi)::value * T] = v[decltype(mi)::value]; });
       }
-      fft_team<N, E, +1, PS, PING, 0>(v, buf0, buf1, tw, t);
+      fft_team<N, E, +1, PS, PING, 0, SH::SYNC>(v, buf0, buf1, tw, t);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
         v[m] = {p * v[m].re, p * v[m].im};
       });
-      fft_team<N, E, -1, PS, PING, (X & 1)>(v, buf0, buf1, tw, t);
+      fft_team<N, E, -1, PS, PING, (X & 1), SH::SYNC>(v, buf0, buf1, tw, t);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         cx<Real> u;
@@ -215,9 +218,9 @@ __global__ void __launch_bounds__((KernelShape<Real, N, E, PS>::THREADS))
         z[m] = {gn * kv.im, -gn * kv.re};
       });
       const cx<Real> *us = stages + stage_offset(nn, s, a.total) + d.offset;
-      fft_team<N, E, +1, PS, PING, 0>(z, buf0, buf1, tw, t);
+      fft_team<N, E, +1, PS, PING, 0, SH::SYNC>(z, buf0, buf1, tw, t);
       sfor<0, E>([&](auto mi) { fa[decltype(mi)::value] = us[t + decltype(mi)::value * T]; });
-      fft_team<N, E, +1, PS, PING, (X & 1)>(fa, buf0, buf1, tw, t);
+      fft_team<N, E, +1, PS, PING, (X & 1), SH::SYNC>(fa, buf0, buf1, tw, t);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const cx<Real> av = fa[m], zv = z[m];
@@ -227,7 +230,7 @@ __global__ void __launch_bounds__((KernelShape<Real, N, E, PS>::THREADS))
         z[m] = {p2 * zv.re + a2.re * zv.re + a2.im * zv.im,
                 p2 * zv.im + a2.im * zv.re - a2.re * zv.im};
       });
-      fft_team<N, E, -1, PS, PING, (2 * X) & 1>(z, buf0, buf1, tw, t);
+      fft_team<N, E, -1, PS, PING, (2 * X) & 1, SH::SYNC>(z, buf0, buf1, tw, t);
       const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kC[s] * h);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__((KernelShape<Real, N, E, PS>::THREADS))
       });
       // the next stage's first transform writes buffer 0 again; parity of
       // this stage's 3 X exchanges may be odd, so fence it
-      if constexpr (PING && ((3 * X) & 1)) __syncthreads();
+      if constexpr (PING && ((3 * X) & 1)) team_sync<SH::SYNC>();
     });
     sfor<0, E>([&](auto mi) { yb1[decltype(mi)::value] = yb[decltype(mi)::value]; });
   }
