@@ -112,7 +112,8 @@ struct Variant {
                    // picture RK4 (cme_rk4ip.hip), 8: interaction-picture RK4 on the
                    // staged transforms (cme_staged.hip), 9: split-step map on the
                    // staged transforms (cme_staged.hip), 10: RK4 with the padded sum
-                   // on the staged transforms (cme_staged.hip)
+                   // on the staged transforms (cme_staged.hip), 11: RK4 with the
+                   // padded sum on the lean kernel (cme_lean.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup

@@ -41,7 +41,9 @@ template <typename Real, int N, int E, int PS> struct LeanShape {
 };
 
 // REC: record the stage inputs and inverse transforms for the adjoint
-template <typename Real, int N, int E, int PS, bool REC>
+// PAD: the alias-free truncated sum, as in the wave kernels: the instance's
+// N/2 modes at transform indices [N/4, 3N/4), the derivative zero elsewhere.
+template <typename Real, int N, int E, int PS, bool REC, bool PAD = false>
 __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
     __attribute__((amdgpu_waves_per_eu(2))) rk4_lean(RunArgs a) {
   using SH = LeanShape<Real, N, E, PS>;
@@ -61,7 +63,11 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
   const DevInst d = a.inst[id];
   cx<Real> *X = lds + sub * SH::PER_INST;
   cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;
-  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + d.offset;
+  static_assert(!(PAD && REC), "padded plans have no adjoint");
+  constexpr int Q4 = N / 4;
+  auto in_band = [](int i) { return !PAD || (i >= Q4 && i < 3 * Q4); };
+  auto phys = [](int i) { return PAD ? i - Q4 : i; };  // index in the caller's state
+  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + (PAD ? d.a_offset : d.offset);
   const double *kap = a.kappa + d.offset;
   const double *omg = a.omega + d.offset;
 
@@ -74,7 +80,7 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
     const int i = WP::mode(w, lane, m);
-    y[m] = A[i];
+    y[m] = in_band(i) ? A[phys(i)] : cx<Real>{(Real)0, (Real)0};
     lr[m] = (Real)(-0.5 * kap[i]);
     om[m] = omg[i];
   });
@@ -127,6 +133,9 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
         if constexpr (m == E / 2) {
           if (pump_owner) kn = cadd(kn, pump);
         }
+        if constexpr (PAD) {
+          if (!in_band(WP::mode(w, lane, m))) kn = {(Real)0, (Real)0};
+        }
         if constexpr (s == 0) acc[m] = kn;
         else {
           const Real wt = (Real)kLeanW[s];
@@ -138,10 +147,11 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
     });
     if (ckpt != nullptr && --to_ckpt == 0) {
       to_ckpt = a.ckpt_every;
-      cx<Real> *dst = ckpt + ckpt_slot * a.total + d.offset;
+      cx<Real> *dst = ckpt + ckpt_slot * a.total + (PAD ? d.a_offset : d.offset);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
-        dst[WP::mode(w, lane, m)] = y[m];
+        const int i = WP::mode(w, lane, m);
+        if (in_band(i)) dst[phys(i)] = y[m];
       });
       ++ckpt_slot;
     }
@@ -149,7 +159,8 @@ __global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
   bool bad = false;
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    A[WP::mode(w, lane, m)] = y[m];
+    const int i = WP::mode(w, lane, m);
+    if (in_band(i)) A[phys(i)] = y[m];
     bad |= !(isfinite(y[m].re) && isfinite(y[m].im));
   });
   if (bad) atomicOr(&a.flags[id], 1);
@@ -296,6 +307,23 @@ hipError_t launch_lean_fwd(const RunArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename Real, int N, int E, int PS>
+hipError_t launch_lean_pad(const RunArgs &a, hipStream_t st) {
+  using SH = LeanShape<Real, N, E, PS>;
+  if (a.stages) return hipErrorInvalidValue;
+  const int grid = (a.count + SH::IPB - 1) / SH::IPB;
+  hipLaunchKernelGGL((rk4_lean<Real, N, E, PS, false, true>), dim3(grid), dim3(SH::THREADS), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+// padded sum (kind 11): transform length N for instances of N/2 modes
+template <typename Real, int N, int E, int PS> constexpr Variant lean_pad_variant() {
+  using SH = LeanShape<Real, N, E, PS>;
+  return Variant{0, N, E, 1, PS, 0, 11, SH::IPB, SH::THREADS, SH::LDS_BYTES,
+                 &launch_lean_pad<Real, N, E, PS>, nullptr};
+}
+
 template <typename Real, int N, int E, int PS> constexpr Variant lean_variant() {
   using SH = LeanShape<Real, N, E, PS>;
   return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, 0, 3, SH::IPB,
@@ -315,6 +343,9 @@ static const Variant kLeanVariants[] = {
     lean_variant<double, 1024, 8, 3>(),
     lean_variant<double, 2048, 8, 3>(),
     lean_variant<double, 4096, 8, 3>(),
+    // the padded sum for 2048-mode instances: eight wavefronts, two per SIMD
+    // (the default there; listed ahead of the wave kernel's padded variant)
+    lean_pad_variant<double, 4096, 8, 3>(),
 };
 
 const Variant *variants_lean(int *count) {

@@ -569,7 +569,7 @@ def _pad_params():
     try:
         from paper_1307_3428_amd import cme as C
         return [(n // 2, k) for n in (256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536)
-                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] in (5, 10)]
+                for k in C.cme_list_kernels(C.CME_F64, n) if C.cme_kernel_info(k)["kind"] in (5, 10, 11)]
     except Exception:
         return [(128, 0)]
 
