@@ -221,8 +221,8 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * two-level transform, 8: interaction-picture RK4 on the staged
  * transforms, 9: split-step map on the staged transforms, 10: RK4 with
  * the padded sum on the staged transforms, 11: RK4 with the padded sum on
- * the two-level transform with twiddles rebuilt on use), instances per
- * workgroup,
+ * the two-level transform with twiddles rebuilt on use, 12: interaction-
+ * picture RK4 on that transform), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all

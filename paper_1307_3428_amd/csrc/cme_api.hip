@@ -131,14 +131,14 @@ bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 const Variant *all_variants(int *count) { return cme::variants(count); }
 
 // kinds 4 and 9 step the split-step map, kinds 5, 10, 11 RK4 with the padded sum,
-// kinds 7 and 8 interaction-picture RK4, all others RK4 with the cyclic sum;
+// kinds 7, 8, 12 interaction-picture RK4, all others RK4 with the cyclic sum;
 // `integrator` encodes both choices as integrator + 16 fwm
 bool integrates(const Variant &v, int integrator) {
   const int fwm = integrator >> 4, integ = integrator & 15;
   if (fwm == CME_FWM_PADDED) return v.kind == 5 || v.kind == 10 || v.kind == 11;
   if (v.kind == 5 || v.kind == 10 || v.kind == 11) return false;
   if (v.kind == 4 || v.kind == 9) return integ == CME_SPLIT_STEP;
-  if (v.kind == 7 || v.kind == 8) return integ == CME_RK4IP;
+  if (v.kind == 7 || v.kind == 8 || v.kind == 12) return integ == CME_RK4IP;
   return integ == CME_RK4;
 }
 

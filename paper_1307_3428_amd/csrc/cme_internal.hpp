@@ -113,7 +113,8 @@ struct Variant {
                    // staged transforms (cme_staged.hip), 9: split-step map on the
                    // staged transforms (cme_staged.hip), 10: RK4 with the padded sum
                    // on the staged transforms (cme_staged.hip), 11: RK4 with the
-                   // padded sum on the lean kernel (cme_lean.hip)
+                   // padded sum on the lean kernel (cme_lean.hip), 12: interaction-
+                   // picture RK4 on the lean kernel (cme_lean.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup

@@ -307,6 +307,144 @@ hipError_t launch_lean_fwd(const RunArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Interaction-picture RK4 (the step of cme_rk4ip.hip) on the lean
+// transforms, for eight wavefronts per instance at two per SIMD: the state y
+// (y_I after the first stage), the accumulated k, the transform array and the
+// per-mode factor exp((-kappa/2 + i omega') h/2) per thread.
+template <typename Real, int N, int E, int PS>
+__global__ void __launch_bounds__((LeanShape<Real, N, E, PS>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(2))) rk4ip_lean(RunArgs a) {
+  using SH = LeanShape<Real, N, E, PS>;
+  using WP = WavePlan<N, E, 1, 0>;
+  constexpr int W = WP::W;
+  __shared__ cx<Real> lds[SH::IPB * SH::PER_INST];
+  const int lane = (int)threadIdx.x & 63;
+  const int wv = (int)threadIdx.x >> 6;
+  const int sub = W == 1 ? wv : 0;
+  const int w = W == 1 ? 0 : wv;
+  const int slot = (int)blockIdx.x * SH::IPB + sub;
+  if constexpr (W == 1) {
+    if (slot >= a.count) return;  // waves of a W = 1 group never synchronise
+  }
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  cx<Real> *X = lds + sub * SH::PER_INST;
+  cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;
+  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + d.offset;
+  const double *kap = a.kappa + d.offset;
+  const double *omg = a.omega + d.offset;
+
+  LeanTw<N, E, Real> tw;
+  load_lean_twiddles<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+
+  const double h = a.h;
+  cx<Real> y[E], acc[E], v[E], dm[E];
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    const int i = WP::mode(w, lane, m);
+    y[m] = A[i];
+    const double mag = exp(-0.25 * h * kap[i]);
+    double sn, cs;
+    sincos(0.5 * h * omg[i], &sn, &cs);
+    dm[m] = {(Real)(mag * cs), (Real)(mag * sn)};
+  });
+  const bool pump_owner = (w == 0 && lane == 0);
+  const Real gn = (Real)d.g0n;
+  const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
+  const Real hh = (Real)(0.5 * h), hf = (Real)h, h6 = (Real)(h / 6.0);
+  cx<Real> *ckpt = reinterpret_cast<cx<Real> *>(a.ckpt);
+  int32_t to_ckpt = a.ckpt_every;
+  int64_t ckpt_slot = 0;
+
+  // v <- N(v) = i (g0/N) DFT(|IDFT v|^2 IDFT v) + pump
+  auto nonlinear = [&]() {
+    lean_fwdpath<N, E, +1, PS, !SH::TWO>(v, X, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
+      v[m] = {p * v[m].re, p * v[m].im};
+    });
+    lean_backpath<N, E, -1, PS>(v, X, Y, tw, w, lane);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      cx<Real> q = {-gn * v[m].im, gn * v[m].re};
+      if constexpr (m == E / 2) {
+        if (pump_owner) q = cadd(q, pump);
+      }
+      v[m] = q;
+    });
+  };
+
+  for (int64_t n = 0; n < a.n_steps; ++n) {
+    const double t0 = (double)(a.step0 + n) * h, tm = t0 + 0.5 * h, t1 = t0 + h;
+    double sn, cs;
+    sincos(-sigma_integral(d.sigma0, d.sigma1, d.tau_ramp, t0, tm), &sn, &cs);
+    const cx<Real> c1 = {(Real)cs, (Real)sn};
+    sincos(-sigma_integral(d.sigma0, d.sigma1, d.tau_ramp, tm, t1), &sn, &cs);
+    const cx<Real> c2 = {(Real)cs, (Real)sn};
+    sfor<0, E>([&](auto mi) { v[decltype(mi)::value] = y[decltype(mi)::value]; });
+    nonlinear();  // k1 = P1 N(y), yI = P1 y
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> p1 = cmul(dm[m], c1);
+      acc[m] = cmul(p1, v[m]);
+      y[m] = cmul(p1, y[m]);
+      v[m] = {y[m].re + hh * acc[m].re, y[m].im + hh * acc[m].im};
+    });
+    nonlinear();  // k2 = N(yI + h/2 k1)
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      acc[m] = {acc[m].re + (Real)2 * v[m].re, acc[m].im + (Real)2 * v[m].im};
+      v[m] = {y[m].re + hh * v[m].re, y[m].im + hh * v[m].im};
+    });
+    nonlinear();  // k3 = N(yI + h/2 k2)
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      acc[m] = {acc[m].re + (Real)2 * v[m].re, acc[m].im + (Real)2 * v[m].im};
+      v[m] = cmul(cmul(dm[m], c2), cx<Real>{y[m].re + hf * v[m].re, y[m].im + hf * v[m].im});
+    });
+    nonlinear();  // k4 = N(P2 (yI + h k3)); y' = P2 (yI + h/6 acc) + h/6 k4
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const cx<Real> z = cmul(cmul(dm[m], c2), cx<Real>{y[m].re + h6 * acc[m].re,
+                                                       y[m].im + h6 * acc[m].im});
+      y[m] = {z.re + h6 * v[m].re, z.im + h6 * v[m].im};
+    });
+    if (ckpt != nullptr && --to_ckpt == 0) {
+      to_ckpt = a.ckpt_every;
+      cx<Real> *dst = ckpt + ckpt_slot * a.total + d.offset;
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        dst[WP::mode(w, lane, m)] = y[m];
+      });
+      ++ckpt_slot;
+    }
+  }
+  bool bad = false;
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    A[WP::mode(w, lane, m)] = y[m];
+    bad |= !(isfinite(y[m].re) && isfinite(y[m].im));
+  });
+  if (bad) atomicOr(&a.flags[id], 1);
+}
+
+template <typename Real, int N, int E, int PS>
+hipError_t launch_rk4ip_lean(const RunArgs &a, hipStream_t st) {
+  using SH = LeanShape<Real, N, E, PS>;
+  if (a.stages) return hipErrorInvalidValue;
+  const int grid = (a.count + SH::IPB - 1) / SH::IPB;
+  hipLaunchKernelGGL((rk4ip_lean<Real, N, E, PS>), dim3(grid), dim3(SH::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
+// interaction-picture RK4 (kind 12)
+template <typename Real, int N, int E, int PS> constexpr Variant rk4ip_lean_variant() {
+  using SH = LeanShape<Real, N, E, PS>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, 0, 12, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES, &launch_rk4ip_lean<Real, N, E, PS>, nullptr};
+}
+
 template <typename Real, int N, int E, int PS>
 hipError_t launch_lean_pad(const RunArgs &a, hipStream_t st) {
   using SH = LeanShape<Real, N, E, PS>;
@@ -346,6 +484,8 @@ static const Variant kLeanVariants[] = {
     // the padded sum for 2048-mode instances: eight wavefronts, two per SIMD
     // (the default there; listed ahead of the wave kernel's padded variant)
     lean_pad_variant<double, 4096, 8, 3>(),
+    // the interaction-picture RK4 at N = 4096 (the default there)
+    rk4ip_lean_variant<double, 4096, 8, 3>(),
 };
 
 const Variant *variants_lean(int *count) {
