@@ -46,9 +46,10 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_staged(&n);
     v.insert(v.end(), a, a + n);
-    a = variants_rk4ip(&n);
-    v.insert(v.end(), a, a + n);
+    // at N = 8192 the staged RK4IP comes first (the wave kernel spills there)
     a = variants_staged_ip(&n);
+    v.insert(v.end(), a, a + n);
+    a = variants_rk4ip(&n);
     v.insert(v.end(), a, a + n);
     a = variants_staged_split(&n);
     v.insert(v.end(), a, a + n);
