@@ -154,6 +154,21 @@ const Variant *default_variant(int precision, int n, int integrator) {
   return nullptr;
 }
 
+// FP64 classic RK4 at N = 8192: the LDS-resident kernel spills and is held
+// to one instance per CU, so up to ~160 instances the staged kernels, which
+// spread each instance over many CUs, are faster (106 vs 134 us per step at
+// 128 instances; 219 vs 145 at 256); this is the default for such classes.
+const Variant *class_default(int precision, int n, int integrator, size_t count) {
+  const Variant *v = default_variant(precision, n, integrator);
+  if (precision == CME_F64 && n == 8192 && integrator == CME_RK4 && count <= 160) {
+    int cnt = 0;
+    const Variant *all = all_variants(&cnt);
+    for (int i = 0; i < cnt; ++i)
+      if (all[i].precision == precision && all[i].n == n && all[i].kind == 6) return &all[i];
+  }
+  return v;
+}
+
 // compiled variants for a precision and size; integrator < 0: any
 std::vector<const Variant *> candidates(int precision, int n, int integrator) {
   int cnt = 0;
@@ -534,7 +549,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
     SizeClass c;
     c.n = g.first;
     c.ids = g.second;
-    c.var = default_variant(precision, c.n, integrator + 16 * fwm);
+    c.var = class_default(precision, c.n, integrator + 16 * fwm, c.ids.size());
     if (!c.var) {
       rc = CME_EUNSUPPORTED;
       break;

@@ -149,12 +149,14 @@ def test_staged_cw_fixed_point_at_full_size(cme):
 
 
 def test_staged_agrees_with_lds_kernel_over_a_longer_run(cme):
-    """N = 8192: the staged variants and the default (LDS-resident) kernel
+    """N = 8192: the staged variants and the LDS-resident kernel
     over 400 steps with checkpoints.  Kernel-against-kernel: both are held
     to the oracle over short runs above; this bounds the drift between the
     two evaluation orders."""
     p = W.pack(moderate_batch(47, [8192] * 3))
-    base, ck0, _, names0 = run(cme, p, 2e-3, 400, ckpt_every=100)
+    wave = [k for k in cme.cme_list_kernels(cme.CME_F64, 8192) if cme.cme_kernel_info(k)["kind"] == 1][0]
+    base, ck0, _, names0 = run(cme, p, 2e-3, 400, select={8192: wave}, ckpt_every=100)
+    assert names0[8192].startswith("rk4_wave")
     for kid in staged_ids(cme, 8192):
         y, ck, st, names = run(cme, p, 2e-3, 400, select={8192: kid}, ckpt_every=100)
         errs = [rel_err(y[p.slice(b)], base[p.slice(b)]) for b in range(3)]
