@@ -1,5 +1,6 @@
-// cme_lean.hip -- two-level RK4 kernels with a small register footprint, so
-// that two wavefronts share each SIMD.
+// cme_lean.hip -- two-level kernels with a small register footprint, so that
+// two wavefronts share each SIMD: classic RK4 (cyclic or padded sum), its
+// reverse sweep, and the interaction-picture RK4.
 //
 // The kernels of cme_wave.hpp keep every per-thread twiddle of the two-level
 // transform in registers and, with the RK4 state, need more than 256

@@ -15,7 +15,9 @@
 // step (the integral of the piecewise-linear ramp in closed form).  The
 // dispersion therefore does not bound the step as it does for classic RK4.
 // Same workgroup layout and transforms as the wave kernels (cme_wave.hpp);
-// four transforms pairs per step, no adjoint.
+// four transform pairs per step, no adjoint.  The same step runs on the lean
+// transforms (cme_lean.hip, N = 4096) and the staged ones (cme_staged.hip,
+// N >= 8192).
 #include <type_traits>
 
 #include "cme_wave.hpp"

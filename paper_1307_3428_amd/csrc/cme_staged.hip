@@ -1,6 +1,9 @@
-// cme_staged.hip -- RK4 for mode counts whose transform does not fit one
-// workgroup (FP64 N >= 8192): four-step transforms whose transpose goes
-// through global memory (L2 / MALL / HBM) instead of LDS.
+// cme_staged.hip -- the solver for transforms that do not fit one workgroup
+// well (N = 8192 ... 65536): four-step transforms whose transpose goes
+// through global memory (L2 / MALL / HBM) instead of LDS.  Classic RK4 (FP64
+// and FP32, cyclic or padded sum), the interaction-picture RK4, the
+// split-step map and the four-wave-mixing sum alone (cme_fwm) run on them;
+// the classic RK4 is described here, the others where they are defined.
 //
 // N = N1 N2; mode index m = m1 + N1 m2 (m1 < N1, m2 < N2); transformed index
 // j = j2 + N2 j1.  With w_L = e^{2 pi i / L} and w = w_N, the inverse
