@@ -153,7 +153,9 @@ int cme_run(cme_plan *plan, void *A, int64_t step0, int64_t n_steps,
  * transforms as Eq. (4) states it: a = IDFT(A), b = |a|^2 a, K = DFT(b) / N.
  *   A  device complex [total], read only (packed like the state)
  *   K  device complex [total], written (same packing; K may not alias A)
- * Plans with CME_FWM_PADDED, and FP32 plans with N > 8192: CME_EUNSUPPORTED.
+ * Plans with CME_FWM_PADDED compute the truncated sum (alpha, beta, gamma
+ * and mu within the instance's modes) on their 2N-point transforms.  FP32
+ * plans with N > 8192: CME_EUNSUPPORTED.
  * Asynchronous on the plan's
  * stream.  Exposes steps a3-a5 of the solver for direct tests. */
 int cme_fwm(cme_plan *plan, const void *A, void *K);

@@ -601,7 +601,6 @@ int cme_step(cme_plan *p, void *A, int64_t step0) { return cme_run(p, A, step0, 
 
 int cme_fwm(cme_plan *p, const void *A, void *K) {
   if (!p || !A || !K) return CME_EINVAL;
-  if (p->fwm != CME_FWM_CYCLIC) return CME_EUNSUPPORTED;
   const size_t nc = p->classes.size();
   if (nc > 1) HIP_TRY(hipEventRecord(p->fork, p->stream));
   for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
@@ -609,7 +608,8 @@ int cme_fwm(cme_plan *p, const void *A, void *K) {
     SizeClass &c = p->classes[i];
     if (c.n > 8192 && (!c.d_work || p->precision != CME_F64)) return CME_EUNSUPPORTED;
     const cme::RunArgs a = run_args(p, c, const_cast<void *>(A), 0, 1, 0, K, nullptr);
-    if (cme::launch_fwm(p->precision, c.n, a, i == 0 ? p->stream : c.side) != hipSuccess)
+    if (cme::launch_fwm(p->precision, c.n, p->fwm == CME_FWM_PADDED, a,
+                        i == 0 ? p->stream : c.side) != hipSuccess)
       return CME_EHIP;
   }
   for (size_t i = 1; i < nc; ++i) {

@@ -13,7 +13,11 @@ namespace cme {
 
 namespace {
 
-template <typename Real, int N, int E, int V, int PS, int TP>
+// PAD: a padded plan's instance of N/2 modes sits at transform indices
+// [N/4, 3N/4) (mode i - N/4 of the caller's arrays), the rest of the input is
+// zero, and only the band is written: the cyclic sum over the zero-padded
+// transform restricted to the band is the truncated sum.
+template <typename Real, int N, int E, int V, int PS, int TP, bool PAD = false>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) fwm_wave(RunArgs a) {
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   using WP = WavePlan<N, E, V, TP>;
@@ -30,12 +34,19 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) f
   const DevInst d = a.inst[a.order[slot]];
   cx<Real> *X = lds + sub * SH::PER_INST;
   cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;
-  const cx<Real> *A = reinterpret_cast<const cx<Real> *>(a.A) + d.offset;
-  cx<Real> *K = reinterpret_cast<cx<Real> *>(a.ckpt) + d.offset;
+  constexpr int Q4 = N / 4;
+  auto in_band = [](int i) { return !PAD || (i >= Q4 && i < 3 * Q4); };
+  auto phys = [](int i) { return PAD ? i - Q4 : i; };
+  const int64_t off = PAD ? d.a_offset : d.offset;
+  const cx<Real> *A = reinterpret_cast<const cx<Real> *>(a.A) + off;
+  cx<Real> *K = reinterpret_cast<cx<Real> *>(a.ckpt) + off;
   WaveTwiddles<N, E, V, TP, Real> tw;
   load_wave_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
   cx<Real> v[E];
-  sfor<0, E>([&](auto mi) { v[decltype(mi)::value] = A[WP::mode(w, lane, decltype(mi)::value)]; });
+  sfor<0, E>([&](auto mi) {
+    const int i = WP::mode(w, lane, decltype(mi)::value);
+    v[decltype(mi)::value] = in_band(i) ? A[phys(i)] : cx<Real>{(Real)0, (Real)0};
+  });
   fft_fwdpath<N, E, V, TP, +1, PS, !SH::TWO>(v, X, tw, w, lane);
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
@@ -46,7 +57,8 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, TP>::THREADS)) f
   const Real inv_n = (Real)1 / (Real)N;
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    K[WP::mode(w, lane, m)] = {v[m].re * inv_n, v[m].im * inv_n};
+    const int i = WP::mode(w, lane, m);
+    if (in_band(i)) K[phys(i)] = {v[m].re * inv_n, v[m].im * inv_n};
   });
 }
 
@@ -78,11 +90,12 @@ __global__ void __launch_bounds__(N / E) fwm_team(RunArgs a) {
   });
 }
 
-template <typename Real, int N, int E, int V, int PS, int TP = 0>
+template <typename Real, int N, int E, int V, int PS, int TP = 0, bool PAD = false>
 hipError_t launch_wave_fwm(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   const int grid = (a.count + SH::IPB - 1) / SH::IPB;
-  hipLaunchKernelGGL((fwm_wave<Real, N, E, V, PS, TP>), dim3(grid), dim3(SH::THREADS), 0, st, a);
+  hipLaunchKernelGGL((fwm_wave<Real, N, E, V, PS, TP, PAD>), dim3(grid), dim3(SH::THREADS), 0, st,
+                     a);
   return hipGetLastError();
 }
 
@@ -107,14 +120,28 @@ template <typename Real> hipError_t launch_fwm_real(int n, const RunArgs &a, hip
   }
 }
 
+// padded plans (FP64): transform length n for instances of n/2 modes
+hipError_t launch_fwm_pad(int n, const RunArgs &a, hipStream_t st) {
+  switch (n) {
+    case 256: return launch_wave_fwm<double, 256, 4, 1, 2, 0, true>(a, st);
+    case 512: return launch_wave_fwm<double, 512, 8, 1, 3, 0, true>(a, st);
+    case 1024: return launch_wave_fwm<double, 1024, 8, 1, 3, 0, true>(a, st);
+    case 2048: return launch_wave_fwm<double, 2048, 8, 1, 3, 0, true>(a, st);
+    case 4096: return launch_wave_fwm<double, 4096, 8, 1, 3, 0, true>(a, st);
+    case 8192: return launch_wave_fwm<double, 8192, 16, 2, 3, 0, true>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 // a.A: input, a.ckpt: output; sizes above 8192 go to the staged transform
-hipError_t launch_staged_fwm(int n, const RunArgs &a, hipStream_t st);  // cme_staged.hip
+hipError_t launch_staged_fwm(int n, bool pad, const RunArgs &a, hipStream_t st);  // cme_staged.hip
 
-hipError_t launch_fwm(int precision, int n, const RunArgs &a, hipStream_t st) {
+hipError_t launch_fwm(int precision, int n, bool pad, const RunArgs &a, hipStream_t st) {
   if (a.count <= 0) return hipSuccess;
-  if (n > 8192) return precision == 0 ? launch_staged_fwm(n, a, st) : hipErrorInvalidValue;
+  if (n > 8192) return precision == 0 ? launch_staged_fwm(n, pad, a, st) : hipErrorInvalidValue;
+  if (pad) return precision == 0 ? launch_fwm_pad(n, a, st) : hipErrorInvalidValue;
   return precision == 0 ? launch_fwm_real<double>(n, a, st) : launch_fwm_real<float>(n, a, st);
 }
 

@@ -141,8 +141,10 @@ const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 // The four-wave-mixing sum alone for one size class (cme_fwm.hip): reads the
 // packed amplitudes at a.A and writes K at a.ckpt (same packing); sizes above
-// 8192 use the staged transform and the class workspace a.work.
-hipError_t launch_fwm(int precision, int n, const RunArgs &a, hipStream_t st);
+// 8192 use the staged transform and the class workspace a.work.  pad: a
+// padded plan's class (transform length n, instances of n/2 modes, the
+// truncated sum).
+hipError_t launch_fwm(int precision, int n, bool pad, const RunArgs &a, hipStream_t st);
 
 // Parameter cotangents of one segment from the stage inputs u_s (a.stages)
 // and the stored kbar_s (a.kbar) of a class of n-mode instances (FP64,

@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
   using SH = ColShape<N, N1, E, WPB>;
   constexpr int N2 = SH::N2, T = SH::T;
   static_assert(!IP || std::is_same<Real, double>::value, "the interaction picture is FP64");
-  static_assert(!PAD || (!IP && STAGE < 4), "the padded sum steps classic RK4");
+  static_assert(!PAD || !IP, "the padded sum steps classic RK4");
   constexpr int Q4 = N / 4;
   auto in_band = [](int i) { return !PAD || (i >= Q4 && i < 3 * Q4); };
   auto phys = [](int i) { return PAD ? i - Q4 : i; };  // index in the caller's state
@@ -164,7 +164,8 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
       const double inv_n = 1.0 / (double)N;
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
-        a.ckpt[d.a_offset + m1 + N1 * (t + m * T)] = dn<Real>({v[m].re * inv_n, v[m].im * inv_n});
+        const int i = m1 + N1 * (t + m * T);
+        if (in_band(i)) a.ckpt[d.a_offset + phys(i)] = dn<Real>({v[m].re * inv_n, v[m].im * inv_n});
       });
       return;
     }
@@ -521,7 +522,7 @@ template <int N, int N1, int E, int WPB> constexpr Variant split_staged_variant(
 
 // The four-wave-mixing sum alone (cme_fwm): r.A in, r.ckpt out, through the
 // class workspace.
-template <int N, int N1, int E, int WPB>
+template <int N, int N1, int E, int WPB, bool PAD>
 hipError_t fwm_staged(const RunArgs &r, hipStream_t st) {
   using CS = ColShape<N, N1, E, WPB>;
   using RS = RowShape<N, N1, E, WPB>;
@@ -539,9 +540,9 @@ hipError_t fwm_staged(const RunArgs &r, hipStream_t st) {
   a.ckpt = reinterpret_cast<cx<double> *>(r.ckpt);
   a.flags = r.flags;
   const dim3 cgrid(r.count * CS::NB), rgrid(r.count * RS::NB), blk(64 * WPB);
-  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1>), cgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, -1, false, double, PAD>), cgrid, blk, 0, st, a);
   hipLaunchKernelGGL((staged_row<N, N1, E, WPB>), rgrid, blk, 0, st, a);
-  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 4>), cgrid, blk, 0, st, a);
+  hipLaunchKernelGGL((staged_col<N, N1, E, WPB, 4, false, double, PAD>), cgrid, blk, 0, st, a);
   return hipGetLastError();
 }
 
@@ -598,11 +599,15 @@ const Variant kStagedIpVariants[] = {
 
 }  // namespace
 
-hipError_t launch_staged_fwm(int n, const RunArgs &r, hipStream_t st) {
+template <int N, int N1> hipError_t fwm_staged_any(bool pad, const RunArgs &r, hipStream_t st) {
+  return pad ? fwm_staged<N, N1, 8, 8, true>(r, st) : fwm_staged<N, N1, 8, 8, false>(r, st);
+}
+
+hipError_t launch_staged_fwm(int n, bool pad, const RunArgs &r, hipStream_t st) {
   switch (n) {
-    case 16384: return fwm_staged<16384, 128, 8, 8>(r, st);
-    case 32768: return fwm_staged<32768, 256, 8, 8>(r, st);
-    case 65536: return fwm_staged<65536, 256, 8, 8>(r, st);
+    case 16384: return fwm_staged_any<16384, 128>(pad, r, st);
+    case 32768: return fwm_staged_any<32768, 256>(pad, r, st);
+    case 65536: return fwm_staged_any<65536, 256>(pad, r, st);
     default: return hipErrorInvalidValue;
   }
 }

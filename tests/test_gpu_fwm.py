@@ -5,7 +5,7 @@ Against the oracle's O(N^2) direct sum on full-support random states at
 every size 16 ... 65536; against closed forms for one and two tones (the
 literal sum over alpha - beta + gamma = mu reduces to a handful of terms);
 and against the identity sum_mu conj(A_mu) K_mu = (1/N) sum_j |a_j|^4 with
-a = N ifft(A) from numpy."""
+a = N ifft(A) from numpy; padded plans against the oracle's truncated sum."""
 import numpy as np
 import pytest
 
@@ -107,10 +107,24 @@ def test_power_identity_against_numpy(cme, n):
     assert abs(lhs.real - rhs) <= 1e-13 * rhs
 
 
-def test_fwm_refused_for_padded_plans(cme):
+@pytest.mark.parametrize("n", [128, 1024, 4096, 8192, 32768])
+def test_fwm_padded_plans_give_the_truncated_sum(cme, orc, n):
+    """Padded plans: the cyclic sum over the zero-padded 2N-point transform,
+    restricted to the instance's modes, is the truncated (literal Kronecker
+    delta) sum; against the oracle's, which differs from the cyclic one."""
     import torch
-    p = W.pack(states(5, [256]))
-    with cme.Plan(p, 1e-3, fwm=cme.CME_FWM_PADDED) as plan:
+    batch = 1 if n >= 8192 else 3
+    p = W.pack(states(400 + n, [n] * batch))
+    with cme.Plan(p, 1e-3, fwm=cme.CME_FWM_PADDED, flags=cme.CME_INIT_SKIP_STABILITY) as plan:
         A = plan.state(p.a0)
-        with pytest.raises(cme.CmeError):
-            plan.fwm(A)
+        K = plan.fwm(A)
+        torch.cuda.synchronize()
+        K = K.cpu().numpy()
+    for b in range(batch):
+        a0 = p.a0[p.slice(b)]
+        ref = orc.fwm(a0, truncated=True)
+        err = float(np.linalg.norm(K[p.slice(b)] - ref) / np.linalg.norm(ref))
+        cyc = orc.fwm(a0)
+        print(f"N={n} instance {b}: {err:.2e}", flush=True)
+        assert err <= 1e-14
+        assert np.linalg.norm(cyc - ref) > 1e-3 * np.linalg.norm(ref)
