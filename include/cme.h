@@ -27,7 +27,7 @@
  *     pump mode mu = 0 is element N/2.  N must be a power of two,
  *     16 <= N <= 65536 (N <= 32768 with the padded sum); above 8192
  *     transform points FP64 with any integrator (classic RK4 for the padded
- *     sum) or FP32 with classic RK4 (CME_EUNSUPPORTED otherwise).
+ *     sum) or FP32 with classic RK4 or RK4IP (CME_EUNSUPPORTED otherwise).
  *   - A batch packs instances back to back; instance b starts at element
  *     inst[b].mode_offset of every per-mode array (state, kappa, omega').
  *     Ranges of different instances must not overlap.  "total" below is the

@@ -445,10 +445,10 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   if (rc != CME_OK) return rc;
   // transforms of up to 65536 points; longer than 8192 only on the staged
   // kernels: FP64 with any integrator (classic RK4 for the padded sum) or
-  // FP32 with classic RK4
+  // FP32 with classic RK4 or RK4IP
   for (int32_t b = 0; b < batch; ++b) {
     const int64_t tn = (fwm == CME_FWM_PADDED ? 2 : 1) * (int64_t)inst[b].n_modes;
-    if (tn > 65536 || (tn > 8192 && precision != CME_F64 && integrator != CME_RK4))
+    if (tn > 65536 || (tn > 8192 && precision != CME_F64 && integrator == CME_SPLIT_STEP))
       return CME_EUNSUPPORTED;
   }
 

@@ -126,7 +126,6 @@ template <int N, int N1, int E, int WPB, int STAGE, bool IP = false, typename Re
 __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
   using SH = ColShape<N, N1, E, WPB>;
   constexpr int N2 = SH::N2, T = SH::T;
-  static_assert(!IP || std::is_same<Real, double>::value, "the interaction picture is FP64");
   static_assert(!PAD || !IP, "the padded sum steps classic RK4");
   constexpr int Q4 = N / 4;
   auto in_band = [](int i) { return !PAD || (i >= Q4 && i < 3 * Q4); };
@@ -186,34 +185,35 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const int i = m1 + N1 * (t + m * T);
-        cx<double> k = {-d.g0n * v[m].im, d.g0n * v[m].re};
+        const cx<double> nk = up(v[m]);
+        cx<double> k = {-d.g0n * nk.im, d.g0n * nk.re};
         if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
         cx<double> nxt;
         if constexpr (STAGE == 0) {
           const cx<double> p1 = prop(i);
-          const cx<double> yi = cmul(p1, A[i]);
+          const cx<double> yi = cmul(p1, up(A[i]));
           const cx<double> k1 = cmul(p1, k);
-          ACC[i] = k1;
-          U[i] = yi;
+          ACC[i] = dn<Real>(k1);
+          U[i] = dn<Real>(yi);
           nxt = {yi.re + 0.5 * h * k1.re, yi.im + 0.5 * h * k1.im};
         } else if constexpr (STAGE == 1) {
-          const cx<double> yi = U[i], acc = ACC[i];
-          ACC[i] = {acc.re + 2.0 * k.re, acc.im + 2.0 * k.im};
+          const cx<double> yi = up(U[i]), acc = up(ACC[i]);
+          ACC[i] = dn<Real>({acc.re + 2.0 * k.re, acc.im + 2.0 * k.im});
           nxt = {yi.re + 0.5 * h * k.re, yi.im + 0.5 * h * k.im};
         } else if constexpr (STAGE == 2) {
-          const cx<double> yi = U[i], acc = ACC[i];
-          ACC[i] = {acc.re + 2.0 * k.re, acc.im + 2.0 * k.im};
+          const cx<double> yi = up(U[i]), acc = up(ACC[i]);
+          ACC[i] = dn<Real>({acc.re + 2.0 * k.re, acc.im + 2.0 * k.im});
           nxt = cmul(prop(i), cx<double>{yi.re + h * k.re, yi.im + h * k.im});
         } else {
-          const cx<double> yi = U[i], acc = ACC[i];
+          const cx<double> yi = up(U[i]), acc = up(ACC[i]);
           const double c = h / 6.0;
           const cx<double> z = cmul(prop(i), cx<double>{yi.re + c * acc.re, yi.im + c * acc.im});
           nxt = {z.re + c * k.re, z.im + c * k.im};
-          A[i] = nxt;
-          if (a.ckpt) a.ckpt[d.a_offset + i] = nxt;
+          A[i] = dn<Real>(nxt);
+          if (a.ckpt) a.ckpt[d.a_offset + i] = dn<Real>(nxt);
           bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
         }
-        v[m] = nxt;
+        v[m] = dn<Real>(nxt);
       });
     } else {
     const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
@@ -595,6 +595,9 @@ const Variant kStagedPadVariants[] = {
 const Variant kStagedIpVariants[] = {
     staged_variant<8192, 128, 8, 8, true>(),  staged_variant<16384, 128, 8, 8, true>(),
     staged_variant<32768, 256, 8, 8, true>(), staged_variant<65536, 256, 8, 8, true>(),
+    // FP32 state and transforms above 8192 (FP64 stage arithmetic)
+    staged_variant<16384, 128, 8, 8, true, float>(), staged_variant<32768, 256, 8, 8, true, float>(),
+    staged_variant<65536, 256, 8, 8, true, float>(),
 };
 
 }  // namespace

@@ -67,7 +67,7 @@ def test_kernel_table_covers_every_size():
             seen.add(k)
         # above 8192 only the staged kernels
         assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8, 9, 10) for k in ids)
-        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] == 6
+        assert n <= 8192 or all(C.cme_kernel_info(k)["kind"] in (6, 8)
                                 for k in C.cme_list_kernels(C.CME_F32, n))
     assert C.cme_list_kernels(C.CME_F64, 100) == []
     assert C.cme_list_kernels(C.CME_F64, 131072) == []
@@ -151,10 +151,10 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
         kw["integrator"] = C.CME_SPLIT_STEP
         expect = C.CME_EUNSUPPORTED
     elif case in ("large_fp32", "large_padded"):
-        # FP32 above 8192 transform points only with classic RK4; at most
-        # 65536 transform points (32768 modes with the padded sum)
+        # no FP32 split-step (at any size); at most 65536 transform points
+        # (32768 modes with the padded sum)
         inst = _inst(n=16384 if case != "large_padded" else 65536)
-        kw.update({"large_fp32": {"precision": C.CME_F32, "integrator": C.CME_RK4IP},
+        kw.update({"large_fp32": {"precision": C.CME_F32, "integrator": C.CME_SPLIT_STEP},
                    "large_padded": {"fwm": C.CME_FWM_PADDED}}[case])
         expect = C.CME_EUNSUPPORTED
     elif case == "split_fp32":

@@ -252,11 +252,11 @@ def test_adjoint_with_staged_forward_uses_a_reverse_capable_kernel(cme):
 
 
 def test_staged_rejects_unsupported_requests(cme):
-    """Above 8192 points: FP32 only with classic RK4, no adjoint, no FP32
+    """Above 8192 points: no FP32 split-step, no adjoint, no FP32
     four-wave-mixing sum alone."""
     p = W.pack(moderate_batch(67, [16384]))
     with pytest.raises(cme.CmeError) as e:
-        cme.Plan(p, 0.01, precision=cme.CME_F32, integrator=cme.CME_RK4IP)
+        cme.Plan(p, 0.01, precision=cme.CME_F32, integrator=cme.CME_SPLIT_STEP)
     assert e.value.code == cme.CME_EUNSUPPORTED
     with cme.Plan(p, 0.01) as plan:
         A0 = plan.state(p.a0)

@@ -193,8 +193,11 @@ def test_gpu_rk4ip_variant_matches_oracle(cme, orc, n, kid):
 @pytest.mark.parametrize("n,kid", _ip_params(1))
 def test_gpu_rk4ip_fp32_variant_matches_fp64_oracle(cme, orc, n, kid):
     batch = 5 if cme.cme_kernel_info(kid)["instances_per_group"] > 1 else 2
+    steps = 4
+    if n >= 32768:   # the oracle's O(N^2) sum costs seconds per evaluation here
+        batch, steps = 1, 2
     p = W.pack(nonlinear_batch(3100 + n, [n] * batch))
-    h, steps = 0.01, 4
+    h = 0.01
     y, _, st, name = gpu_ip(cme, p, h, steps, step0=5, precision=1, kid=kid)
     ref = orc.rk4ip_run(p, h, steps, step0=5)
     errs = [rel_err(y[p.slice(b)], ref[p.slice(b)]) for b in range(batch)]
