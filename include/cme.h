@@ -120,7 +120,8 @@ typedef struct cme_plan cme_plan;
  *          only) or
  *          CME_SPLIT_STEP (frequency-domain Strang split-step, Sec. 2: exact
  *          linear half steps per mode around the exact Kerr phase rotation
- *          of the transformed field; FP64 only, N >= 128, no adjoint).
+ *          of the transformed field; N >= 128, FP32 up to N = 4096, no
+ *          adjoint).
  *   fwm    CME_FWM_CYCLIC or CME_FWM_PADDED (see above).
  *   h      step size (> 0) in the time units of kappa.
  *   stream hipStream_t the plan enqueues on (NULL: the null stream).

@@ -435,7 +435,6 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   if ((integrator != CME_RK4 && integrator != CME_RK4IP && integrator != CME_SPLIT_STEP) ||
       (fwm != CME_FWM_CYCLIC && fwm != CME_FWM_PADDED))
     return CME_EINVAL;
-  if (integrator == CME_SPLIT_STEP && precision != CME_F64) return CME_EUNSUPPORTED;
   if (fwm == CME_FWM_PADDED && (precision != CME_F64 || integrator != CME_RK4))
     return CME_EUNSUPPORTED;
   if (!(h > 0.0) || !std::isfinite(h)) return CME_EINVAL;

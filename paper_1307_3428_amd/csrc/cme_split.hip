@@ -17,8 +17,9 @@
 // e^{L_mu h/2} = e^{(-kappa_mu/2 + i omega'_mu) h/2} e^{-i sigma h/2}: the
 // first factor is formed once per launch, the second once per half step.
 // Two transforms per step (RK4 needs eight); second-order accurate in h.
-// The transform is that of cme_lean.hpp; FP64; N = 128 ... 4096 (the staged
-// transforms of cme_staged.hip take the same map above).
+// The transform is that of cme_lean.hpp; FP64 or FP32 (the linear factors
+// formed in FP64 and rounded, the pump mode's half step in FP64); N = 128 ...
+// 4096 (the staged transforms of cme_staged.hip take the same map above, FP64).
 #include <type_traits>
 
 #include "cme_internal.hpp"
@@ -46,7 +47,6 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
   using SH = SplitShape<Real, N, E, PS, IPB_>;
   using WP = WavePlan<N, E, 1, 0>;
   constexpr int W = WP::W;
-  static_assert(std::is_same<Real, double>::value, "the split-step kernels are FP64");
   __shared__ cx<Real> lds[SH::IPB * SH::PER_INST];
 
   const int lane = (int)threadIdx.x & 63;
@@ -78,11 +78,11 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
     const double mag = exp(-0.5 * kap[i] * hh);
     double sn, cs;
     sincos(omg[i] * hh, &sn, &cs);
-    f[m] = {mag * cs, mag * sn};
+    f[m] = {(Real)(mag * cs), (Real)(mag * sn)};
   });
   const bool pump_owner = (w == 0 && lane == 0);  // mode N/2 sits in slot E/2
   const double lre = -0.5 * kap[N / 2], lim0 = omg[N / 2];
-  const cx<Real> pump = {d.pump_re, d.pump_im};
+  const cx<double> pump = {d.pump_re, d.pump_im};
   const double gh = d.g0n * (double)N * h;  // g0 h
   const Real inv_n = (Real)1 / (Real)N;
 
@@ -90,27 +90,33 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
     const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t_mid);
     double sn, cs;
     sincos(-sig * hh, &sn, &cs);
-    const cx<Real> c = {cs, sn};
+    const cx<Real> c = {(Real)cs, (Real)sn};
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      const cx<Real> e = cmul(f[m], c);
-      y[m] = cmul(y[m], e);
+      bool pumped = false;
       if constexpr (m == E / 2) {
         if (pump_owner) {
-          // (e - 1) / L with L = lre + i (lim0 - sig), or its small-|L h/2| limit
-          const cx<Real> L = {lre, lim0 - sig};
-          const double lh = sqrt(L.re * L.re + L.im * L.im) * hh;
-          cx<Real> phi;
-          if (lh > 1e-8) {
-            const cx<Real> em1 = {e.re - 1.0, e.im};
-            const double den = L.re * L.re + L.im * L.im;
-            phi = {(em1.re * L.re + em1.im * L.im) / den, (em1.im * L.re - em1.re * L.im) / den};
+          // the pump mode in FP64: e = exp(L h/2) with L = lre + i (lim0 - sig),
+          // and (e - 1) / L, or its small-|L h/2| limit, times the drive
+          const double li = lim0 - sig;
+          const double mg = exp(lre * hh);
+          double s2, c2;
+          sincos(li * hh, &s2, &c2);
+          const cx<double> e = {mg * c2, mg * s2};
+          cx<double> phi;
+          if (sqrt(lre * lre + li * li) * hh > 1e-8) {
+            const double den = lre * lre + li * li;
+            phi = {((e.re - 1.0) * lre + e.im * li) / den, (e.im * lre - (e.re - 1.0) * li) / den};
           } else {
-            phi = {hh * (1.0 + 0.5 * L.re * hh), hh * (0.5 * L.im * hh)};
+            phi = {hh * (1.0 + 0.5 * lre * hh), hh * (0.5 * li * hh)};
           }
-          y[m] = cadd(y[m], cmul(pump, phi));
+          const cx<double> yd = cadd(cmul(cx<double>{(double)y[m].re, (double)y[m].im}, e),
+                                     cmul(pump, phi));
+          y[m] = {(Real)yd.re, (Real)yd.im};
+          pumped = true;
         }
       }
+      if (!pumped) y[m] = cmul(y[m], cmul(f[m], c));
     });
   };
 
@@ -126,7 +132,7 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
       constexpr int m = decltype(mi)::value;
       double sn, cs;
       sincos(gh * (v[m].re * v[m].re + v[m].im * v[m].im), &sn, &cs);
-      v[m] = cmul(v[m], cx<Real>{cs, sn});
+      v[m] = cmul(v[m], cx<Real>{(Real)cs, (Real)sn});
     });
     lean_backpath<N, E, -1, PS>(v, X, Y, tw, w, lane);
     sfor<0, E>([&](auto mi) {
@@ -163,7 +169,8 @@ hipError_t launch_split(const RunArgs &a, hipStream_t st) {
 
 template <typename Real, int N, int E, int PS, int IPB_ = 0> constexpr Variant split_variant() {
   using SH = SplitShape<Real, N, E, PS, IPB_>;
-  return Variant{0, N, E, 1, PS, 0, 4, SH::IPB, SH::THREADS, SH::LDS_BYTES,
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, 1, PS, 0, 4, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES,
                  &launch_split<Real, N, E, PS, IPB_>, nullptr};
 }
 
@@ -176,6 +183,11 @@ static const Variant kSplitVariants[] = {
     split_variant<double, 128, 2, 1>(),    split_variant<double, 256, 4, 2>(),
     split_variant<double, 512, 8, 3>(),    split_variant<double, 1024, 8, 3>(),
     split_variant<double, 2048, 8, 3>(),   split_variant<double, 4096, 8, 3>(),
+    // FP32 state and transforms (the linear factors formed in FP64, the pump
+    // mode's half step in FP64)
+    split_variant<float, 128, 2, 1, 1>(), split_variant<float, 256, 4, 2, 1>(),
+    split_variant<float, 512, 8, 3>(),    split_variant<float, 1024, 8, 3>(),
+    split_variant<float, 2048, 8, 3>(),   split_variant<float, 4096, 8, 3>(),
 };
 
 const Variant *variants_split(int *count) {

@@ -97,7 +97,7 @@ def _init_raw(inst, kappa, omega, h=0.01, precision=0, flags=0, batch=None, plan
 @pytest.mark.parametrize("case", ["null_plan", "batch0", "null_kappa", "bad_n", "n_too_big",
                                   "n_too_small", "neg_h", "nan_h", "bad_precision",
                                   "reserved", "neg_offset", "overlap", "bad_flags",
-                                  "nan_sigma", "neg_kext", "bad_integrator", "split_fp32",
+                                  "nan_sigma", "neg_kext", "bad_integrator",
                                   "bad_fwm", "padded_split", "large_fp32", "large_padded",
                                   "rk4ip_padded"])
 def test_init_rejects_invalid_arguments_without_a_device(case):
@@ -156,10 +156,6 @@ def test_init_rejects_invalid_arguments_without_a_device(case):
         inst = _inst(n=16384 if case != "large_padded" else 65536)
         kw.update({"large_fp32": {"precision": C.CME_F32, "integrator": C.CME_SPLIT_STEP},
                    "large_padded": {"fwm": C.CME_FWM_PADDED}}[case])
-        expect = C.CME_EUNSUPPORTED
-    elif case == "split_fp32":
-        kw["integrator"] = C.CME_SPLIT_STEP
-        kw["precision"] = C.CME_F32
         expect = C.CME_EUNSUPPORTED
     rc, handle = _init_raw(inst, kappa, omega, **kw)
     assert rc == expect, (case, rc)

@@ -517,6 +517,38 @@ def test_split_step_fig1_ensemble(cme, orc):
     assert max(errs) <= 1e-10, errs
 
 
+def _split_params_f32():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096)
+                for k in C.cme_list_kernels(C.CME_F32, n) if C.cme_kernel_info(k)["kind"] == 4]
+    except Exception:
+        return [(128, 0)]
+
+
+@pytest.mark.parametrize("n,kid", _split_params_f32())
+def test_split_step_fp32_variant_matches_fp64_oracle(cme, orc, n, kid):
+    """FP32 state and transforms, linear factors and the pump mode in FP64;
+    20 steps accumulate a few 1e-6 of FP32 rounding (the FP32 bar is 1e-4)."""
+    import torch
+    batch = 2
+    p = W.pack(moderate_batch(5100 + n, [n] * batch))
+    steps, h = 20, 0.01
+    with cme.Plan(p, h, precision=cme.CME_F32, integrator=cme.CME_SPLIT_STEP) as plan:
+        plan.select(n, kid)
+        A = plan.state(p.a0)
+        assert A.dtype == torch.complex64
+        plan.run(A, steps, step0=3)
+        torch.cuda.synchronize()
+        y = A.cpu().numpy().astype(np.complex128)
+        assert not plan.status().any()
+        name = plan.kernel(n)["name"]
+    ref = orc.split_step_run(p, h, steps, step0=3)
+    errs = per_instance_err(p, y, ref)
+    print(name, errs, flush=True)
+    assert max(errs) <= 1e-5, errs
+
+
 @pytest.mark.parametrize("n,batch", [(2048, 4), (65536, 2)])
 def test_split_step_is_unitary_without_loss_and_pump(cme, n, batch):
     """With kappa = 0 and no pump every part of the split-step map is
