@@ -93,30 +93,49 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
     const cx<Real> c = {(Real)cs, (Real)sn};
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      bool pumped = false;
-      if constexpr (m == E / 2) {
+      const cx<Real> e = cmul(f[m], c);
+      if constexpr (m == E / 2 && std::is_same<Real, float>::value) {
         if (pump_owner) {
-          // the pump mode in FP64: e = exp(L h/2) with L = lre + i (lim0 - sig),
-          // and (e - 1) / L, or its small-|L h/2| limit, times the drive
+          // FP32: the pump mode's half step in FP64, where (e - 1) / L would
+          // lose digits: e = exp(L h/2) with L = lre + i (lim0 - sig)
           const double li = lim0 - sig;
           const double mg = exp(lre * hh);
           double s2, c2;
           sincos(li * hh, &s2, &c2);
-          const cx<double> e = {mg * c2, mg * s2};
+          const cx<double> ed = {mg * c2, mg * s2};
           cx<double> phi;
           if (sqrt(lre * lre + li * li) * hh > 1e-8) {
             const double den = lre * lre + li * li;
-            phi = {((e.re - 1.0) * lre + e.im * li) / den, (e.im * lre - (e.re - 1.0) * li) / den};
+            phi = {((ed.re - 1.0) * lre + ed.im * li) / den, (ed.im * lre - (ed.re - 1.0) * li) / den};
           } else {
             phi = {hh * (1.0 + 0.5 * lre * hh), hh * (0.5 * li * hh)};
           }
-          const cx<double> yd = cadd(cmul(cx<double>{(double)y[m].re, (double)y[m].im}, e),
+          const cx<double> yd = cadd(cmul(cx<double>{(double)y[m].re, (double)y[m].im}, ed),
                                      cmul(pump, phi));
           y[m] = {(Real)yd.re, (Real)yd.im};
-          pumped = true;
+        } else {
+          y[m] = cmul(y[m], e);
+        }
+      } else {
+        y[m] = cmul(y[m], e);
+        if constexpr (m == E / 2) {
+          if (pump_owner) {
+            // (e - 1) / L with L = lre + i (lim0 - sig), or its small-|L h/2| limit
+            const cx<double> L = {lre, lim0 - sig};
+            const double lh = sqrt(L.re * L.re + L.im * L.im) * hh;
+            cx<double> phi;
+            if (lh > 1e-8) {
+              const cx<double> em1 = {e.re - 1.0, e.im};
+              const double den = L.re * L.re + L.im * L.im;
+              phi = {(em1.re * L.re + em1.im * L.im) / den, (em1.im * L.re - em1.re * L.im) / den};
+            } else {
+              phi = {hh * (1.0 + 0.5 * L.re * hh), hh * (0.5 * L.im * hh)};
+            }
+            const cx<double> pp = cmul(pump, phi);
+            y[m] = {y[m].re + (Real)pp.re, y[m].im + (Real)pp.im};
+          }
         }
       }
-      if (!pumped) y[m] = cmul(y[m], cmul(f[m], c));
     });
   };
 
