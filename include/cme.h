@@ -213,19 +213,21 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
 /* Shape of variant kernel_id, written into info[0..min(cap, 10)-1]:
  * precision, modes N, modes per thread E, wave-local sub-transforms per wave
  * V, LDS padding shift (one pad element every 2^shift), kind (0: one
- * transform per team of threads with workgroup barriers, 1: two-level
+ * transform per team of threads, ordered by workgroup barriers, or at
+ * wavefront scope when the workgroup is one wavefront, 1: two-level
  * transform with one workgroup barrier per transform, 2: two-level
  * transforms in four rounds of two interleaved transforms per RK4 step,
  * 3: two-level transform with twiddles rebuilt on use, sized for two
  * wavefronts per SIMD, 4: split-step map, 5: RK4 with the padded sum on
  * N-point transforms for instances of N/2 modes, 6: four-step transforms
- * staged through global memory, several workgroups per instance, with the
- * row length N1 in the V field, 7: interaction-picture RK4 on the
+ * staged through global memory, several workgroups per instance, 7:
+ * interaction-picture RK4 on the
  * two-level transform, 8: interaction-picture RK4 on the staged
  * transforms, 9: split-step map on the staged transforms, 10: RK4 with
  * the padded sum on the staged transforms, 11: RK4 with the padded sum on
  * the two-level transform with twiddles rebuilt on use, 12: interaction-
- * picture RK4 on that transform), instances per workgroup,
+ * picture RK4 on that transform; the staged kinds 6, 8, 9, 10 carry the
+ * row length N1 in the V field), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
