@@ -286,3 +286,22 @@ def test_gpu_rk4ip_split_runs_and_checkpoints_are_bitwise(cme):
         assert torch.equal(A, B)
         for s in range(3):
             assert torch.equal(ck[s], mids[s])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n,steps,h", [(1024, 300, 2e-3), (4096, 100, 2e-3), (16384, 10, 5e-3)])
+def test_gpu_rk4ip_longer_runs_match_oracle(cme, orc, n, steps, h):
+    """Longer RK4IP runs against the oracle (the default kernel of each size:
+    wave, lean, staged), with checkpoints."""
+    batch = 2 if n <= 4096 else 1
+    p = W.pack(nonlinear_batch(3300 + n, [n] * batch))
+    y, ck, st, name = gpu_ip(cme, p, h, steps, ckpt_every=steps // 2)
+    ref = orc.rk4ip_run(p, h, steps)
+    mid = orc.rk4ip_run(p, h, steps // 2)
+    for b in range(batch):
+        err = rel_err(y[p.slice(b)], ref[p.slice(b)])
+        cerr = rel_err(ck[0][p.slice(b)], mid[p.slice(b)])
+        moved = rel_err(p.a0[p.slice(b)], ref[p.slice(b)])
+        print(f"{name} N={n} instance {b}: {err:.2e}, checkpoint {cerr:.2e} (moved {moved:.2e})")
+        assert err <= 1e-11 and cerr <= 1e-11 and moved > 0.1
+    assert not st.any()
