@@ -266,3 +266,30 @@ def test_staged_rejects_unsupported_requests(cme):
         A0 = plan.state(p.a0)
         with pytest.raises(cme.CmeError):
             plan.fwm(A0)
+
+
+def test_staged_padded_and_split_longer_runs_match_oracle(cme, orc):
+    """The padded sum (8192 modes on 16384-point staged transforms, 20 RK4
+    steps) and the split-step map (N = 16384, 30 steps) against the oracle,
+    checkpoints included."""
+    import torch
+    for kind, n, steps, h in (("padded", 8192, 20, 5e-3), ("split", 16384, 30, 5e-3)):
+        p = W.pack(moderate_batch(2200 + n, [n]))
+        kw = {"fwm": cme.CME_FWM_PADDED} if kind == "padded" else {"integrator": cme.CME_SPLIT_STEP}
+        with cme.Plan(p, h, **kw) as plan:
+            A = plan.state(p.a0)
+            ck = torch.zeros((2, p.total), dtype=A.dtype, device=A.device)
+            plan.run(A, steps, ckpt_every=steps // 2, ckpt=ck)
+            torch.cuda.synchronize()
+            y, ck = A.cpu().numpy(), ck.cpu().numpy()
+            name = plan.kernel(n)["name"]
+            assert not plan.status().any()
+        if kind == "padded":
+            ref, _ = orc.run(p, h, steps, truncated=True)
+            mid, _ = orc.run(p, h, steps // 2, truncated=True)
+        else:
+            ref = orc.split_step_run(p, h, steps)
+            mid = orc.split_step_run(p, h, steps // 2)
+        err, cerr, moved = rel_err(y, ref), rel_err(ck[0], mid), rel_err(p.a0, ref)
+        print(f"{name}: {err:.2e}, checkpoint {cerr:.2e} (moved {moved:.2e})", flush=True)
+        assert err <= 1e-11 and cerr <= 1e-11 and moved > 0.05
