@@ -61,12 +61,19 @@ enum {
   CME_ENOMEM = -2,       /* device or host allocation failed                */
   CME_EHIP = -3,         /* a HIP runtime call failed                       */
   CME_EUNSTABLE = -4,    /* classic RK4 step outside its stability region:
-                            h * max_mu |-kappa_mu/2 + i(omega'_mu - sigma)|
-                            > 2 sqrt(2) for some instance and detuning      */
+                            |R(h (-kappa_mu/2 + i(omega'_mu - sigma)))| > 1
+                            for some mode, instance and detuning, with
+                            R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24           */
   CME_ENONFINITE = -5,   /* non-finite input (kappa, omega', pump, ...)    */
   CME_EUNSUPPORTED = -6, /* valid request the library does not provide     */
-  CME_ENODEVICE = -7     /* no gfx950 device / kernels not loadable        */
+  CME_ENODEVICE = -7,    /* no gfx950 device / kernels not loadable        */
+  CME_ESCRATCH = -8      /* cme_adjoint_noalloc: the request needs more than
+                            CME_NOALLOC_SCRATCH_BYTES of scratch            */
 };
+
+/* Size of the library's fixed device scratch array (one per GPU, held until
+ * the process ends), the only working memory of cme_adjoint_noalloc. */
+#define CME_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
 
 enum { CME_F64 = 0, CME_F32 = 1 };        /* arithmetic precision            */
 enum { CME_RK4 = 0, CME_RK4IP = 1, CME_SPLIT_STEP = 2 }; /* integrator       */
@@ -183,6 +190,28 @@ int cme_fwm(cme_plan *plan, const void *A, void *K);
 int cme_adjoint(cme_plan *plan, const void *A0, const void *ckpt, int64_t step0,
                 int64_t n_steps, int32_t ckpt_every, const void *gA_T, void *gA_0,
                 double *g_omega, double *g_kappa, double *g_ain);
+
+/* cme_adjoint without allocation, for callers that cannot allocate device
+ * memory while they run (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and
+ * restrictions as cme_adjoint, computed by the same kernels; it calls no
+ * hipMalloc, hipFree or other allocating routine and creates no stream or
+ * event.  Its working memory is the library's fixed device array of
+ * CME_NOALLOC_SCRATCH_BYTES (one copy per GPU), laid out per call as
+ *   one stage-record buffer   8 * K * total complex values
+ *   kbar of the segment       4 * K * total (the FP64 two-level kernels)
+ *   state and cotangent       2 * total
+ *   segment starts            (ceil(n_steps / K) - 1) * total, only if ckpt is NULL
+ * with K = min(ckpt_every, n_steps) (n_steps if ckpt_every is 0), each part
+ * rounded up to 256 bytes; a larger request returns CME_ESCRATCH before
+ * anything is enqueued.  The recompute of each segment and its reverse sweep
+ * run one after the other on the plan's stream (cme_adjoint overlaps them on
+ * a second stream), so it is slower.  Every call on a GPU uses the same
+ * array: calls that overlap in time on one GPU (two streams, two threads)
+ * race and must not be issued. */
+int cme_adjoint_noalloc(cme_plan *plan, const void *A0, const void *ckpt, int64_t step0,
+                        int64_t n_steps, int32_t ckpt_every, const void *gA_T, void *gA_0,
+                        double *g_omega, double *g_kappa, double *g_ain);
 
 /* Synchronise the plan's stream and report per-instance status into the host
  * array flags[batch] (0: finite; 1: a non-finite amplitude was seen).  Returns

@@ -21,13 +21,16 @@ LIB_PATH = os.path.join(_HERE, "libcme.so")
 
 CME_OK, CME_EINVAL, CME_ENOMEM, CME_EHIP = 0, -1, -2, -3
 CME_EUNSTABLE, CME_ENONFINITE, CME_EUNSUPPORTED, CME_ENODEVICE = -4, -5, -6, -7
+CME_ESCRATCH = -8
+CME_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 CME_F64, CME_F32 = 0, 1
 CME_RK4, CME_RK4IP, CME_SPLIT_STEP = 0, 1, 2
 CME_FWM_CYCLIC, CME_FWM_PADDED = 0, 1
 CME_INIT_DEFAULT, CME_INIT_SKIP_STABILITY, CME_INIT_AUTOTUNE = 0, 1, 2
 
 EXPORTED = (
-    "cme_init", "cme_step", "cme_run", "cme_fwm", "cme_adjoint", "cme_status", "cme_set_stream",
+    "cme_init", "cme_step", "cme_run", "cme_fwm", "cme_adjoint", "cme_adjoint_noalloc",
+    "cme_status", "cme_set_stream",
     "cme_plan_kernel", "cme_plan_select", "cme_list_kernels", "cme_kernel_info", "cme_destroy",
     "cme_strerror", "cme_version",
 )
@@ -76,6 +79,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cme_run": (ctypes.c_int, [P, P, i64, i64, i32, P]),
         "cme_fwm": (ctypes.c_int, [P, P, P]),
         "cme_adjoint": (ctypes.c_int, [P, P, P, i64, i64, i32, P, P, P, P, P]),
+        "cme_adjoint_noalloc": (ctypes.c_int, [P, P, P, i64, i64, i32, P, P, P, P, P]),
         "cme_status": (ctypes.c_int, [P, P]),
         "cme_set_stream": (ctypes.c_int, [P, P]),
         "cme_plan_kernel": (ctypes.c_int, [P, i32, P]),
@@ -173,6 +177,13 @@ def cme_adjoint(plan: int, A0, ckpt, step0: int, n_steps: int, ckpt_every: int, 
     _check(load_library().cme_adjoint(plan, _dptr(A0), _dptr(ckpt), int(step0), int(n_steps),
                                       int(ckpt_every), _dptr(gA_T), _dptr(gA_0), _dptr(g_omega),
                                       _dptr(g_kappa), _dptr(g_ain)), "cme_adjoint")
+
+
+def cme_adjoint_noalloc(plan: int, A0, ckpt, step0: int, n_steps: int, ckpt_every: int, gA_T,
+                        gA_0=None, g_omega=None, g_kappa=None, g_ain=None) -> None:
+    _check(load_library().cme_adjoint_noalloc(
+        plan, _dptr(A0), _dptr(ckpt), int(step0), int(n_steps), int(ckpt_every), _dptr(gA_T),
+        _dptr(gA_0), _dptr(g_omega), _dptr(g_kappa), _dptr(g_ain)), "cme_adjoint_noalloc")
 
 
 def cme_status(plan: int, batch: int) -> np.ndarray:

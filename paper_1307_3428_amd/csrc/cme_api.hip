@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -62,7 +63,29 @@ const Variant *variants(int *count) {
 }
 }  // namespace cme
 
+// Fixed device scratch of cme_adjoint_noalloc: every GPU the library runs on
+// holds one copy of it until the process ends.  Host code never uses this
+// name as an address; it uses the per-device pointer from scratch_on().
+static __device__ __align__(256) unsigned char scratch[CME_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+// Device address of `scratch` on `device`, which must be current: looked up
+// once per device and kept.
+int scratch_on(int device, void **out) {
+  static std::mutex mu;
+  static void *addr[256] = {};
+  if (device < 0 || device >= 256) return CME_ENODEVICE;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return CME_EHIP;
+    addr[device] = ptr;
+  }
+  *out = addr[device];
+  return CME_OK;
+}
 
 struct SizeClass {
   int n = 0;
@@ -118,6 +141,8 @@ struct cme_plan {
   hipEvent_t adj_entry = nullptr;
   hipEvent_t rec_done[2] = {nullptr, nullptr};
   hipEvent_t rev_done[2] = {nullptr, nullptr};
+  // this device's copy of the library's fixed scratch array (cme_adjoint_noalloc)
+  void *d_scratch = nullptr;
 };
 
 namespace {
@@ -405,6 +430,165 @@ int validate_instances(int32_t batch, const cme_instance *inst, int64_t *total) 
   return CME_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Adjoint (cme_adjoint and its allocation-free variant share all of this).
+
+struct AdjCall {
+  const void *A0;
+  const void *ckpt;
+  int64_t step0, n_steps;
+  int32_t ckpt_every;
+  const void *gA_T;
+  void *gA_0;
+  double *g_omega, *g_kappa, *g_ain;
+};
+
+struct AdjShape {
+  int64_t K = 0, nseg = 0;
+  size_t vec = 0;          // bytes of one packed state
+  size_t stage_bytes = 0;  // one stage-record buffer: u_s and a_s of K steps
+  size_t kbar_bytes = 0;   // kbar_s of K steps (0: no class stores them)
+  size_t ckpt_bytes = 0;   // segment starts of the adjoint's own forward pass
+};
+
+struct AdjBuffers {
+  void *stages[2];  // record buffers of alternate segments (equal when !overlap)
+  void *kbar;
+  void *state;
+  void *gA;
+  void *ckpt;
+  bool overlap;     // recompute on the adjoint's stream beside the reverse sweep
+};
+
+int adjoint_check(const cme_plan *p, const AdjCall &c) {
+  if (!p || !c.A0 || !c.gA_T || c.step0 < 0 || c.n_steps < 0 || c.ckpt_every < 0)
+    return CME_EINVAL;
+  if (c.ckpt && c.ckpt_every == 0) return CME_EINVAL;
+  if (p->precision != CME_F64 || p->integrator != CME_RK4 || p->fwm != CME_FWM_CYCLIC)
+    return CME_EUNSUPPORTED;
+  for (const auto &cl : p->classes)
+    if (!adjoint_variant(p, cl)) return CME_EUNSUPPORTED;
+  if (c.n_steps == 0 && c.gA_0) {
+    HIP_TRY(hipMemcpyAsync(c.gA_0, c.gA_T, p->elem * (size_t)p->total, hipMemcpyDefault,
+                           p->stream));
+  }
+  return CME_OK;
+}
+
+// A class whose forward kernel has no reverse sweep (the staged kernels)
+// recomputes and reverses with a variant of its size that has one; the
+// forward kernels are restored when this goes out of scope.  Fixed storage:
+// at most one class per power of two from 16 to 65536.
+struct VariantSwap {
+  cme_plan *p;
+  const Variant *saved[16] = {};
+  bool ok = true;
+  explicit VariantSwap(cme_plan *q) : p(q) {
+    if (p->classes.size() > 16) {
+      ok = false;
+      return;
+    }
+    for (size_t i = 0; i < p->classes.size(); ++i) {
+      saved[i] = p->classes[i].var;
+      p->classes[i].var = adjoint_variant(p, p->classes[i]);
+    }
+  }
+  ~VariantSwap() {
+    if (!ok) return;
+    for (size_t i = 0; i < p->classes.size(); ++i) p->classes[i].var = saved[i];
+  }
+};
+
+AdjShape adjoint_shape(const cme_plan *p, const AdjCall &c) {
+  AdjShape s;
+  s.K = c.ckpt_every > 0 ? std::min<int64_t>(c.ckpt_every, c.n_steps) : c.n_steps;
+  s.nseg = (c.n_steps + s.K - 1) / s.K;
+  s.vec = p->elem * (size_t)p->total;
+  s.stage_bytes = s.vec * 8 * (size_t)s.K;
+  bool kbar = false;
+  for (const auto &cl : p->classes) kbar |= cl.var->adj_kbar != 0;
+  s.kbar_bytes = kbar ? s.vec * 4 * (size_t)s.K : 0;
+  s.ckpt_bytes = (!c.ckpt && s.nseg > 1) ? s.vec * (size_t)(s.nseg - 1) : 0;
+  return s;
+}
+
+// Checkpointed recomputation and the reverse sweep, segment by segment from
+// the last.  With b.overlap the recompute of segment s - 1 runs on the
+// adjoint's stream beside the reverse sweep of segment s (two record
+// buffers; events order each buffer's reuse and join every recompute back
+// into the plan's stream); without it everything runs in order on the
+// plan's stream with one record buffer.
+int adjoint_run(cme_plan *p, const AdjCall &c, const AdjShape &s, const AdjBuffers &b) {
+  const size_t vec = s.vec;
+  const int64_t K = s.K, nseg = s.nseg, n_steps = c.n_steps, step0 = c.step0;
+  const unsigned char *ck = (const unsigned char *)c.ckpt;
+  int rc = CME_OK;
+  if (!ck && nseg > 1) {
+    // no checkpoints given: run the forward pass once, keeping segment starts
+    HIP_TRY(hipMemcpyAsync(b.state, c.A0, vec, hipMemcpyDefault, p->stream));
+    rc = launch_forward(p, b.state, step0, (nseg - 1) * K, (int32_t)K, b.ckpt, nullptr);
+    if (rc != CME_OK) return rc;
+    ck = (const unsigned char *)b.ckpt;
+  }
+  HIP_TRY(hipMemcpyAsync(b.gA, c.gA_T, vec, hipMemcpyDefault, p->stream));
+  hipStream_t rs = b.overlap ? p->adj_stream : p->stream;  // the recompute's stream
+  if (b.overlap) {
+    HIP_TRY(hipEventRecord(p->adj_entry, p->stream));
+    HIP_TRY(hipStreamWaitEvent(p->adj_stream, p->adj_entry, 0));
+  }
+  auto recompute = [&](int64_t seg) -> int {
+    const int k = (int)(seg & 1);
+    const int64_t first = seg * K;
+    const int64_t len = std::min<int64_t>(K, n_steps - first);
+    // the reverse sweep of segment seg + 2 read this buffer last
+    if (b.overlap && seg + 2 < nseg) HIP_TRY(hipStreamWaitEvent(rs, p->rev_done[k], 0));
+    const void *start = seg == 0 ? c.A0 : (const void *)(ck + (size_t)(seg - 1) * vec);
+    HIP_TRY(hipMemcpyAsync(b.state, start, vec, hipMemcpyDefault, rs));
+    const int r = launch_forward(p, b.state, step0 + first, len, 0, nullptr, b.stages[k], rs);
+    if (r != CME_OK) return r;
+    if (b.overlap) HIP_TRY(hipEventRecord(p->rec_done[k], rs));
+    return CME_OK;
+  };
+  if (b.overlap && (rc = recompute(nseg - 1)) != CME_OK) return rc;
+  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+    const int k = (int)(seg & 1);
+    const int64_t first = seg * K;
+    const int64_t len = std::min<int64_t>(K, n_steps - first);
+    if (b.overlap) {
+      if (seg >= 1 && (rc = recompute(seg - 1)) != CME_OK) return rc;
+      HIP_TRY(hipStreamWaitEvent(p->stream, p->rec_done[k], 0));
+    } else if ((rc = recompute(seg)) != CME_OK) {
+      return rc;
+    }
+    for (auto &cl : p->classes) {
+      cme::AdjArgs a{};
+      a.inst = p->d_inst;
+      a.order = cl.d_order;
+      a.count = (int32_t)cl.ids.size();
+      a.n_seg = (int32_t)len;
+      a.stages = b.stages[k];
+      a.gA = b.gA;
+      a.kappa = p->d_kappa;
+      a.omega = p->d_omega;
+      a.twiddle = cl.d_tw;
+      a.h = p->h;
+      a.step_first = step0 + first;
+      a.total = p->total;
+      a.g_omega = c.g_omega;
+      a.g_kappa = c.g_kappa;
+      a.g_ain = c.g_ain;
+      a.kbar = cl.var->adj_kbar ? b.kbar : nullptr;
+      if (cl.var->adj(a, p->stream) != hipSuccess) return CME_EHIP;
+      if (cl.var->adj_kbar && cme::launch_adj_params(cl.n, a, p->stream) != hipSuccess)
+        return CME_EHIP;
+    }
+    if (b.overlap) HIP_TRY(hipEventRecord(p->rev_done[k], p->stream));
+  }
+  if (c.gA_0) HIP_TRY(hipMemcpyAsync(c.gA_0, b.gA, vec, hipMemcpyDefault, p->stream));
+  return CME_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -421,6 +605,7 @@ const char *cme_strerror(int code) {
     case CME_ENONFINITE: return "non-finite value";
     case CME_EUNSUPPORTED: return "unsupported request";
     case CME_ENODEVICE: return "no gfx950 device available";
+    case CME_ESCRATCH: return "request exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status code";
   }
 }
@@ -456,6 +641,8 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return CME_ENODEVICE;
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return CME_ENODEVICE;
+  void *scratch_ptr = nullptr;
+  if (int r = scratch_on(device, &scratch_ptr); r != CME_OK) return r;
 
   // parameters to the host for validation (kappa / omega may be host or device)
   std::vector<double> hk((size_t)total), ho((size_t)total);
@@ -478,6 +665,7 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
   cme_plan *p = new (std::nothrow) cme_plan();
   if (!p) return CME_ENOMEM;
   p->device = device;
+  p->d_scratch = scratch_ptr;
   p->stream = (hipStream_t)stream;
   p->batch = batch;
   p->precision = precision;
@@ -621,112 +809,61 @@ int cme_fwm(cme_plan *p, const void *A, void *K) {
 int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, int64_t n_steps,
                 int32_t ckpt_every, const void *gA_T, void *gA_0, double *g_omega,
                 double *g_kappa, double *g_ain) {
-  if (!p || !A0 || !gA_T || step0 < 0 || n_steps < 0 || ckpt_every < 0) return CME_EINVAL;
-  if (ckpt && ckpt_every == 0) return CME_EINVAL;
-  if (p->precision != CME_F64 || p->integrator != CME_RK4 || p->fwm != CME_FWM_CYCLIC)
-    return CME_EUNSUPPORTED;
-  // A class whose forward kernel has no reverse sweep (the staged kernels)
-  // recomputes and reverses with a variant of its size that has one; the
-  // forward kernels are restored on return.
-  std::vector<const Variant *> fwd_vars;
-  for (auto &c : p->classes) {
-    fwd_vars.push_back(c.var);
-    if (!adjoint_variant(p, c)) return CME_EUNSUPPORTED;
-  }
-  struct Restore {
-    cme_plan *p;
-    const std::vector<const Variant *> &v;
-    ~Restore() {
-      for (size_t i = 0; i < p->classes.size(); ++i) p->classes[i].var = v[i];
-    }
-  } restore{p, fwd_vars};
-  for (auto &c : p->classes) c.var = adjoint_variant(p, c);
-  const size_t vec = p->elem * (size_t)p->total;
-  if (n_steps == 0) {
-    if (gA_0) HIP_TRY(hipMemcpyAsync(gA_0, gA_T, vec, hipMemcpyDefault, p->stream));
-    return CME_OK;
-  }
-  const int64_t K = ckpt_every > 0 ? std::min<int64_t>(ckpt_every, n_steps) : n_steps;
-  if (K > (1 << 20)) return CME_EINVAL;
-  const int64_t nseg = (n_steps + K - 1) / K;
-  int rc = grow(&p->d_stages, &p->stages_bytes, vec * 8 * (size_t)K);
-  if (rc != CME_OK) return rc;
-  if (nseg > 1 && (rc = grow(&p->d_stages2, &p->stages2_bytes, vec * 8 * (size_t)K)) != CME_OK)
+  AdjCall c{A0, ckpt, step0, n_steps, ckpt_every, gA_T, gA_0, g_omega, g_kappa, g_ain};
+  int rc = adjoint_check(p, c);
+  if (rc != CME_OK || n_steps == 0) return rc;
+  VariantSwap swap(p);
+  if (!swap.ok) return CME_EUNSUPPORTED;
+  const AdjShape s = adjoint_shape(p, c);
+  if (s.K > (1 << 20)) return CME_EINVAL;
+  AdjBuffers b{};
+  if ((rc = grow(&p->d_stages, &p->stages_bytes, s.stage_bytes)) != CME_OK) return rc;
+  if (s.nseg > 1 && (rc = grow(&p->d_stages2, &p->stages2_bytes, s.stage_bytes)) != CME_OK)
     return rc;
-  rc = grow(&p->d_state, &p->state_bytes, vec);
-  if (rc != CME_OK) return rc;
-  rc = grow(&p->d_gA, &p->gA_bytes, vec);
-  if (rc != CME_OK) return rc;
-  bool kbar = false;
-  for (auto &c : p->classes) kbar |= c.var->adj_kbar != 0;
-  if (kbar && (rc = grow(&p->d_kbar, &p->kbar_bytes, vec * 4 * (size_t)K)) != CME_OK) return rc;
+  if ((rc = grow(&p->d_state, &p->state_bytes, s.vec)) != CME_OK) return rc;
+  if ((rc = grow(&p->d_gA, &p->gA_bytes, s.vec)) != CME_OK) return rc;
+  if (s.kbar_bytes && (rc = grow(&p->d_kbar, &p->kbar_bytes, s.kbar_bytes)) != CME_OK) return rc;
+  if (s.ckpt_bytes && (rc = grow(&p->d_ckpt, &p->ckpt_bytes, s.ckpt_bytes)) != CME_OK) return rc;
   if ((rc = adjoint_streams(p)) != CME_OK) return rc;
-  const unsigned char *ck = (const unsigned char *)ckpt;
-  if (!ck && nseg > 1) {
-    // no checkpoints given: run the forward pass once, keeping segment starts
-    rc = grow(&p->d_ckpt, &p->ckpt_bytes, vec * (size_t)(nseg - 1));
-    if (rc != CME_OK) return rc;
-    HIP_TRY(hipMemcpyAsync(p->d_state, A0, vec, hipMemcpyDefault, p->stream));
-    rc = launch_forward(p, p->d_state, step0, (nseg - 1) * K, (int32_t)K, p->d_ckpt, nullptr);
-    if (rc != CME_OK) return rc;
-    ck = (const unsigned char *)p->d_ckpt;
-  }
-  HIP_TRY(hipMemcpyAsync(p->d_gA, gA_T, vec, hipMemcpyDefault, p->stream));
-  // The segment recomputes run on the adjoint's stream, the reverse sweeps on
-  // the plan's stream: the recompute of segment s - 1 needs only its
-  // checkpoint, so it runs beside the reverse sweep of segment s (two record
-  // buffers, used by alternate segments).  Events order each buffer's reuse
-  // and join every recompute back into the plan's stream.
-  void *bufs[2] = {p->d_stages, nseg > 1 ? p->d_stages2 : p->d_stages};
-  HIP_TRY(hipEventRecord(p->adj_entry, p->stream));
-  HIP_TRY(hipStreamWaitEvent(p->adj_stream, p->adj_entry, 0));
-  auto recompute = [&](int64_t seg) -> int {
-    const int b = (int)(seg & 1);
-    const int64_t first = seg * K;
-    const int64_t len = std::min<int64_t>(K, n_steps - first);
-    // the reverse sweep of segment seg + 2 read this buffer last
-    if (seg + 2 < nseg) HIP_TRY(hipStreamWaitEvent(p->adj_stream, p->rev_done[b], 0));
-    const void *start = seg == 0 ? A0 : (const void *)(ck + (size_t)(seg - 1) * vec);
-    HIP_TRY(hipMemcpyAsync(p->d_state, start, vec, hipMemcpyDefault, p->adj_stream));
-    const int r = launch_forward(p, p->d_state, step0 + first, len, 0, nullptr, bufs[b],
-                                 p->adj_stream);
-    if (r != CME_OK) return r;
-    HIP_TRY(hipEventRecord(p->rec_done[b], p->adj_stream));
-    return CME_OK;
-  };
-  if ((rc = recompute(nseg - 1)) != CME_OK) return rc;
-  for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-    const int b = (int)(seg & 1);
-    const int64_t first = seg * K;
-    const int64_t len = std::min<int64_t>(K, n_steps - first);
-    if (seg >= 1 && (rc = recompute(seg - 1)) != CME_OK) return rc;
-    HIP_TRY(hipStreamWaitEvent(p->stream, p->rec_done[b], 0));
-    for (auto &c : p->classes) {
-      cme::AdjArgs a{};
-      a.inst = p->d_inst;
-      a.order = c.d_order;
-      a.count = (int32_t)c.ids.size();
-      a.n_seg = (int32_t)len;
-      a.stages = bufs[b];
-      a.gA = p->d_gA;
-      a.kappa = p->d_kappa;
-      a.omega = p->d_omega;
-      a.twiddle = c.d_tw;
-      a.h = p->h;
-      a.step_first = step0 + first;
-      a.total = p->total;
-      a.g_omega = g_omega;
-      a.g_kappa = g_kappa;
-      a.g_ain = g_ain;
-      a.kbar = c.var->adj_kbar ? p->d_kbar : nullptr;
-      if (c.var->adj(a, p->stream) != hipSuccess) return CME_EHIP;
-      if (c.var->adj_kbar && cme::launch_adj_params(c.n, a, p->stream) != hipSuccess)
-        return CME_EHIP;
-    }
-    HIP_TRY(hipEventRecord(p->rev_done[b], p->stream));
-  }
-  if (gA_0) HIP_TRY(hipMemcpyAsync(gA_0, p->d_gA, vec, hipMemcpyDefault, p->stream));
-  return CME_OK;
+  b.stages[0] = p->d_stages;
+  b.stages[1] = s.nseg > 1 ? p->d_stages2 : p->d_stages;
+  b.kbar = p->d_kbar;
+  b.state = p->d_state;
+  b.gA = p->d_gA;
+  b.ckpt = p->d_ckpt;
+  b.overlap = true;
+  return adjoint_run(p, c, s, b);
+}
+
+int cme_adjoint_noalloc(cme_plan *p, const void *A0, const void *ckpt, int64_t step0,
+                        int64_t n_steps, int32_t ckpt_every, const void *gA_T, void *gA_0,
+                        double *g_omega, double *g_kappa, double *g_ain) {
+  AdjCall c{A0, ckpt, step0, n_steps, ckpt_every, gA_T, gA_0, g_omega, g_kappa, g_ain};
+  int rc = adjoint_check(p, c);
+  if (rc != CME_OK || n_steps == 0) return rc;
+  void *base = p->d_scratch;
+  if (!base) return CME_EHIP;
+  VariantSwap swap(p);
+  if (!swap.ok) return CME_EUNSUPPORTED;
+  const AdjShape s = adjoint_shape(p, c);
+  // one stage-record buffer (no overlap), then kbar, the state, the cotangent
+  // and the forward pass's segment starts, each at a 256-byte boundary
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t need = up(s.stage_bytes) + up(s.kbar_bytes) + 2 * up(s.vec) + up(s.ckpt_bytes);
+  if (s.K > (1 << 20) || need > (size_t)CME_NOALLOC_SCRATCH_BYTES) return CME_ESCRATCH;
+  unsigned char *q = (unsigned char *)base;
+  AdjBuffers b{};
+  b.stages[0] = b.stages[1] = q;
+  q += up(s.stage_bytes);
+  b.kbar = s.kbar_bytes ? (void *)q : nullptr;
+  q += up(s.kbar_bytes);
+  b.state = q;
+  q += up(s.vec);
+  b.gA = q;
+  q += up(s.vec);
+  b.ckpt = s.ckpt_bytes ? (void *)q : nullptr;
+  b.overlap = false;
+  return adjoint_run(p, c, s, b);
 }
 
 int cme_status(cme_plan *p, int32_t *flags) {

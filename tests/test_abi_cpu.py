@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_strerror_and_version():
-    for code in (0, -1, -2, -3, -4, -5, -6, -7):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
         s = C.cme_strerror(code)
         assert s and s != "unknown status code"
     assert C.cme_strerror(-99) == "unknown status code"
