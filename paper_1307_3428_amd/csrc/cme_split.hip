@@ -84,6 +84,7 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
   const double lre = -0.5 * kap[N / 2], lim0 = omg[N / 2];
   const cx<double> pump = {d.pump_re, d.pump_im};
   const double gh = d.g0n * (double)N * h;  // g0 h
+  const Real ghr = (Real)gh;                 // the Kerr rotation runs in Real
   const Real inv_n = (Real)1 / (Real)N;
 
   auto half_linear = [&](double t_mid) {
@@ -96,8 +97,10 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
       const cx<Real> e = cmul(f[m], c);
       if constexpr (m == E / 2 && std::is_same<Real, float>::value) {
         if (pump_owner) {
-          // FP32: the pump mode's half step in FP64, where (e - 1) / L would
-          // lose digits: e = exp(L h/2) with L = lre + i (lim0 - sig)
+          // FP32: the pump mode's half-step coefficients e = exp(L h/2) and
+          // s (e - 1) / L with L = lre + i (lim0 - sig) depend on sigma(t);
+          // they are formed in FP64 (in FP32, e - 1 would lose digits) and
+          // rounded once, the update of the state is FP32
           const double li = lim0 - sig;
           const double mg = exp(lre * hh);
           double s2, c2;
@@ -110,9 +113,9 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
           } else {
             phi = {hh * (1.0 + 0.5 * lre * hh), hh * (0.5 * li * hh)};
           }
-          const cx<double> yd = cadd(cmul(cx<double>{(double)y[m].re, (double)y[m].im}, ed),
-                                     cmul(pump, phi));
-          y[m] = {(Real)yd.re, (Real)yd.im};
+          const cx<double> sp = cmul(pump, phi);
+          y[m] = cadd(cmul(y[m], cx<Real>{(Real)ed.re, (Real)ed.im}),
+                      cx<Real>{(Real)sp.re, (Real)sp.im});
         } else {
           y[m] = cmul(y[m], e);
         }
@@ -149,9 +152,11 @@ __global__ void __launch_bounds__((SplitShape<Real, N, E, PS, IPB_>::THREADS)) s
     lean_fwdpath<N, E, +1, PS, !SH::TWO>(v, X, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      double sn, cs;
-      sincos(gh * (v[m].re * v[m].re + v[m].im * v[m].im), &sn, &cs);
-      v[m] = cmul(v[m], cx<Real>{(Real)cs, (Real)sn});
+      Real sn, cs;
+      const Real ph = ghr * (v[m].re * v[m].re + v[m].im * v[m].im);
+      if constexpr (std::is_same<Real, float>::value) sincosf(ph, &sn, &cs);
+      else sincos(ph, &sn, &cs);
+      v[m] = cmul(v[m], cx<Real>{cs, sn});
     });
     lean_backpath<N, E, -1, PS>(v, X, Y, tw, w, lane);
     sfor<0, E>([&](auto mi) {

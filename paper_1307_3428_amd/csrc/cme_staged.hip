@@ -39,8 +39,8 @@ namespace cme {
 
 namespace {
 
-// Real: the precision of the state, the transforms and the stored arrays
-// (FP64, or FP32 for classic RK4); the stage arithmetic is done in FP64.
+// Real: the precision of the state, the transforms, the stored arrays and
+// the stage arithmetic (FP64, or FP32 for classic RK4 and RK4IP).
 template <typename Real> struct StagedArgsT {
   const DevInst *inst;
   const int32_t *order;
@@ -58,9 +58,6 @@ template <typename Real> struct StagedArgsT {
 };
 using StagedArgs = StagedArgsT<double>;
 
-template <typename Real> __device__ __forceinline__ cx<double> up(cx<Real> z) {
-  return {(double)z.re, (double)z.im};
-}
 template <typename Real> __device__ __forceinline__ cx<Real> dn(cx<double> z) {
   return {(Real)z.re, (Real)z.im};
 }
@@ -168,8 +165,13 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
       });
       return;
     }
+    // The stage arithmetic runs in Real; only the time-dependent coefficients
+    // (sigma(t), omega' - sigma, the propagators' phase with the integral of
+    // sigma) are formed in FP64 and rounded to Real once per stage.
     const double h = a.h;
     const double *kap = a.kappa + d.offset, *omg = a.omega + d.offset;
+    const Real gn = (Real)d.g0n;
+    const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
     bool bad = false;
     if constexpr (IP) {
       // detuning phase of the half step whose propagator this stage applies
@@ -180,77 +182,77 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
         const double mag = exp(-0.25 * h * kap[i]);
         double sn, cs;
         sincos(0.5 * h * omg[i] - sg, &sn, &cs);
-        return cx<double>{mag * cs, mag * sn};
+        return cx<Real>{(Real)(mag * cs), (Real)(mag * sn)};
       };
+      const Real h2 = (Real)(0.5 * h), h1 = (Real)h, h6 = (Real)(h / 6.0), two = (Real)2;
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const int i = m1 + N1 * (t + m * T);
-        const cx<double> nk = up(v[m]);
-        cx<double> k = {-d.g0n * nk.im, d.g0n * nk.re};
-        if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
-        cx<double> nxt;
+        const cx<Real> nk = v[m];
+        cx<Real> k = {-gn * nk.im, gn * nk.re};
+        if (i == N / 2) k = cadd(k, pump);
+        cx<Real> nxt;
         if constexpr (STAGE == 0) {
-          const cx<double> p1 = prop(i);
-          const cx<double> yi = cmul(p1, up(A[i]));
-          const cx<double> k1 = cmul(p1, k);
-          ACC[i] = dn<Real>(k1);
-          U[i] = dn<Real>(yi);
-          nxt = {yi.re + 0.5 * h * k1.re, yi.im + 0.5 * h * k1.im};
+          const cx<Real> p1 = prop(i);
+          const cx<Real> yi = cmul(p1, A[i]);
+          const cx<Real> k1 = cmul(p1, k);
+          ACC[i] = k1;
+          U[i] = yi;
+          nxt = {yi.re + h2 * k1.re, yi.im + h2 * k1.im};
         } else if constexpr (STAGE == 1) {
-          const cx<double> yi = up(U[i]), acc = up(ACC[i]);
-          ACC[i] = dn<Real>({acc.re + 2.0 * k.re, acc.im + 2.0 * k.im});
-          nxt = {yi.re + 0.5 * h * k.re, yi.im + 0.5 * h * k.im};
+          const cx<Real> yi = U[i], acc = ACC[i];
+          ACC[i] = {acc.re + two * k.re, acc.im + two * k.im};
+          nxt = {yi.re + h2 * k.re, yi.im + h2 * k.im};
         } else if constexpr (STAGE == 2) {
-          const cx<double> yi = up(U[i]), acc = up(ACC[i]);
-          ACC[i] = dn<Real>({acc.re + 2.0 * k.re, acc.im + 2.0 * k.im});
-          nxt = cmul(prop(i), cx<double>{yi.re + h * k.re, yi.im + h * k.im});
+          const cx<Real> yi = U[i], acc = ACC[i];
+          ACC[i] = {acc.re + two * k.re, acc.im + two * k.im};
+          nxt = cmul(prop(i), cx<Real>{yi.re + h1 * k.re, yi.im + h1 * k.im});
         } else {
-          const cx<double> yi = up(U[i]), acc = up(ACC[i]);
-          const double c = h / 6.0;
-          const cx<double> z = cmul(prop(i), cx<double>{yi.re + c * acc.re, yi.im + c * acc.im});
-          nxt = {z.re + c * k.re, z.im + c * k.im};
-          A[i] = dn<Real>(nxt);
-          if (a.ckpt) a.ckpt[d.a_offset + i] = dn<Real>(nxt);
+          const cx<Real> yi = U[i], acc = ACC[i];
+          const cx<Real> z = cmul(prop(i), cx<Real>{yi.re + h6 * acc.re, yi.im + h6 * acc.im});
+          nxt = {z.re + h6 * k.re, z.im + h6 * k.im};
+          A[i] = nxt;
+          if (a.ckpt) a.ckpt[d.a_offset + i] = nxt;
           bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
         }
-        v[m] = dn<Real>(nxt);
+        v[m] = nxt;
       });
     } else {
     const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
+    const Real cn = (Real)(STAGE == 0 || STAGE == 1 ? 0.5 * h : h), h6 = (Real)(h / 6.0);
+    const Real two = (Real)2;
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const int i = m1 + N1 * (t + m * T);
       const bool band = in_band(i);
-      const cx<double> y = band ? up(A[phys(i)]) : cx<double>{0.0, 0.0};
-      const cx<double> u = STAGE == 0 ? y : up(U[i]);
-      const cx<double> nk = up(v[m]);
-      const double lr = -0.5 * kap[i], li = omg[i] - sig;
+      const cx<Real> y = band ? A[phys(i)] : cx<Real>{(Real)0, (Real)0};
+      const cx<Real> u = STAGE == 0 ? y : U[i];
+      const cx<Real> nk = v[m];
+      const Real lr = (Real)(-0.5 * kap[i]), li = (Real)(omg[i] - sig);
       // k = L u + i (g0/N) N K
-      cx<double> k = {lr * u.re - li * u.im - d.g0n * nk.im, lr * u.im + li * u.re + d.g0n * nk.re};
-      if (i == N / 2) k = cadd(k, cx<double>{d.pump_re, d.pump_im});
-      if (!band) k = {0.0, 0.0};
-      cx<double> nxt;
+      cx<Real> k = {lr * u.re - li * u.im - gn * nk.im, lr * u.im + li * u.re + gn * nk.re};
+      if (i == N / 2) k = cadd(k, pump);
+      if (!band) k = {(Real)0, (Real)0};
+      cx<Real> nxt;
       if constexpr (STAGE == 0) {
-        ACC[i] = dn<Real>(k);
-        nxt = {y.re + 0.5 * h * k.re, y.im + 0.5 * h * k.im};
-        U[i] = dn<Real>(nxt);
+        ACC[i] = k;
+        nxt = {y.re + cn * k.re, y.im + cn * k.im};
+        U[i] = nxt;
       } else if constexpr (STAGE < 3) {
-        const cx<double> acc = up(ACC[i]);
-        ACC[i] = dn<Real>({acc.re + 2.0 * k.re, acc.im + 2.0 * k.im});
-        const double c = STAGE == 1 ? 0.5 * h : h;
-        nxt = {y.re + c * k.re, y.im + c * k.im};
-        U[i] = dn<Real>(nxt);
+        const cx<Real> acc = ACC[i];
+        ACC[i] = {acc.re + two * k.re, acc.im + two * k.im};
+        nxt = {y.re + cn * k.re, y.im + cn * k.im};
+        U[i] = nxt;
       } else {
-        const cx<double> acc = up(ACC[i]);
-        const double c = h / 6.0;
-        nxt = {y.re + c * (acc.re + k.re), y.im + c * (acc.im + k.im)};
+        const cx<Real> acc = ACC[i];
+        nxt = {y.re + h6 * (acc.re + k.re), y.im + h6 * (acc.im + k.im)};
         if (band) {
-          A[phys(i)] = dn<Real>(nxt);
-          if (a.ckpt) a.ckpt[d.a_offset + phys(i)] = dn<Real>(nxt);
+          A[phys(i)] = nxt;
+          if (a.ckpt) a.ckpt[d.a_offset + phys(i)] = nxt;
         }
         bad |= !(isfinite(nxt.re) && isfinite(nxt.im));
       }
-      v[m] = dn<Real>(nxt);
+      v[m] = nxt;
     });
     }
     if constexpr (STAGE == 3) {
