@@ -45,6 +45,8 @@ const Variant *variants(int *count) {
     v.insert(v.end(), a, a + n);
     a = variants_wave_f32(&n);
     v.insert(v.end(), a, a + n);
+    a = variants_stream(&n);
+    v.insert(v.end(), a, a + n);
     a = variants_staged(&n);
     v.insert(v.end(), a, a + n);
     // at N = 8192 the staged RK4IP comes first (the wave kernel spills there)
@@ -327,21 +329,49 @@ cme::RunArgs run_args(const cme_plan *p, const SizeClass &c, void *A, int64_t st
 // chip, and the call stays ordered on the caller's stream (and capturable
 // into a graph, where it becomes parallel branches).
 // (on `base`, the plan's stream unless the adjoint's own stream is given)
+// Fork the side streams of classes 1..nc-1 from `base`; returns how many
+// were forked (a failure part way leaves the earlier ones forked).
+size_t fork_classes(cme_plan *p, hipStream_t base, int *rc) {
+  const size_t nc = p->classes.size();
+  *rc = CME_OK;
+  if (nc <= 1) return 0;
+  if (hipEventRecord(p->fork, base) != hipSuccess) {
+    *rc = CME_EHIP;
+    return 0;
+  }
+  size_t forked = 0;
+  for (size_t i = 1; i < nc; ++i, ++forked)
+    if (hipStreamWaitEvent(p->classes[i].side, p->fork, 0) != hipSuccess) {
+      *rc = CME_EHIP;
+      break;
+    }
+  return forked;
+}
+
+// Join the first `forked` side streams back into `base`, also after a
+// failure, so that no fork is left open (under graph capture, an unjoined
+// fork invalidates the capture).
+int join_classes(cme_plan *p, hipStream_t base, size_t forked) {
+  int rc = CME_OK;
+  for (size_t i = 1; i <= forked; ++i)
+    if (hipEventRecord(p->classes[i].done, p->classes[i].side) != hipSuccess ||
+        hipStreamWaitEvent(base, p->classes[i].done, 0) != hipSuccess)
+      rc = CME_EHIP;
+  return rc;
+}
+
 int launch_forward(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
                    void *ckpt, void *stages, hipStream_t base) {
   const size_t nc = p->classes.size();
-  if (nc > 1) HIP_TRY(hipEventRecord(p->fork, base));
-  for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
-  for (size_t i = 0; i < nc; ++i) {
+  int rc = CME_OK;
+  const size_t forked = fork_classes(p, base, &rc);
+  for (size_t i = 0; i < nc && rc == CME_OK; ++i) {
     SizeClass &c = p->classes[i];
     const cme::RunArgs a = run_args(p, c, A, step0, n_steps, ckpt_every, ckpt, stages);
-    if (c.var->fwd(a, i == 0 ? base : c.side) != hipSuccess) return CME_EHIP;
+    if (c.var->fwd(a, i == 0 ? base : c.side) != hipSuccess) rc = CME_EHIP;
   }
-  for (size_t i = 1; i < nc; ++i) {
-    HIP_TRY(hipEventRecord(p->classes[i].done, p->classes[i].side));
-    HIP_TRY(hipStreamWaitEvent(base, p->classes[i].done, 0));
-  }
-  return CME_OK;
+  const int jr = join_classes(p, base, forked);
+  return rc != CME_OK ? rc : jr;
 }
 
 int launch_forward(cme_plan *p, void *A, int64_t step0, int64_t n_steps, int32_t ckpt_every,
@@ -789,21 +819,20 @@ int cme_step(cme_plan *p, void *A, int64_t step0) { return cme_run(p, A, step0, 
 int cme_fwm(cme_plan *p, const void *A, void *K) {
   if (!p || !A || !K) return CME_EINVAL;
   const size_t nc = p->classes.size();
-  if (nc > 1) HIP_TRY(hipEventRecord(p->fork, p->stream));
-  for (size_t i = 1; i < nc; ++i) HIP_TRY(hipStreamWaitEvent(p->classes[i].side, p->fork, 0));
-  for (size_t i = 0; i < nc; ++i) {
-    SizeClass &c = p->classes[i];
+  // every class is checked before anything is enqueued
+  for (const SizeClass &c : p->classes)
     if (c.n > 8192 && (!c.d_work || p->precision != CME_F64)) return CME_EUNSUPPORTED;
+  int rc = CME_OK;
+  const size_t forked = fork_classes(p, p->stream, &rc);
+  for (size_t i = 0; i < nc && rc == CME_OK; ++i) {
+    SizeClass &c = p->classes[i];
     const cme::RunArgs a = run_args(p, c, const_cast<void *>(A), 0, 1, 0, K, nullptr);
     if (cme::launch_fwm(p->precision, c.n, p->fwm == CME_FWM_PADDED, a,
                         i == 0 ? p->stream : c.side) != hipSuccess)
-      return CME_EHIP;
+      rc = CME_EHIP;
   }
-  for (size_t i = 1; i < nc; ++i) {
-    HIP_TRY(hipEventRecord(p->classes[i].done, p->classes[i].side));
-    HIP_TRY(hipStreamWaitEvent(p->stream, p->classes[i].done, 0));
-  }
-  return CME_OK;
+  const int jr = join_classes(p, p->stream, forked);
+  return rc != CME_OK ? rc : jr;
 }
 
 int cme_adjoint(cme_plan *p, const void *A0, const void *ckpt, int64_t step0, int64_t n_steps,
