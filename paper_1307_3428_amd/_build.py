@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libcme.so")
-SOURCES = ["cme_wave.hip", "cme_wave_f32.hip", "cme_lean.hip", "cme_duo.hip", "cme_split.hip", "cme_staged.hip", "cme_rk4ip.hip", "cme_fwm.hip", "cme_kernels.hip", "cme_api.hip"]
+SOURCES = ["cme_wave.hip", "cme_wave_f32.hip", "cme_lean.hip", "cme_duo.hip", "cme_split.hip", "cme_staged.hip", "cme_stream.hip", "cme_rk4ip.hip", "cme_fwm.hip", "cme_kernels.hip", "cme_api.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are disabled for all device code.

@@ -114,7 +114,9 @@ struct Variant {
                    // staged transforms (cme_staged.hip), 10: RK4 with the padded sum
                    // on the staged transforms (cme_staged.hip), 11: RK4 with the
                    // padded sum on the lean kernel (cme_lean.hip), 12: interaction-
-                   // picture RK4 on the lean kernel (cme_lean.hip)
+                   // picture RK4 on the lean kernel (cme_lean.hip), 13: RK4 on the
+                   // two-level transform with the RK4 vectors in global memory
+                   // (cme_stream.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup
@@ -137,6 +139,7 @@ const Variant *variants_rk4ip(int *count);   // cme_rk4ip.hip
 const Variant *variants_staged_ip(int *count);  // cme_staged.hip (interaction picture)
 const Variant *variants_staged_split(int *count);  // cme_staged.hip (split-step)
 const Variant *variants_staged_pad(int *count);    // cme_staged.hip (padded sum)
+const Variant *variants_stream(int *count);   // cme_stream.hip
 const Variant *variants(int *count);       // all of them (cme_api.hip)
 
 // The four-wave-mixing sum alone for one size class (cme_fwm.hip): reads the

@@ -1,0 +1,278 @@
+// cme_stream.hip -- classic RK4 on the two-level transform of cme_fft.hpp with
+// the RK4 vectors kept in global memory instead of registers.
+//
+// For the largest LDS-resident transforms (N = 8192: 128 KiB of FP64 field,
+// one instance per CU) a thread owns 16 modes, and holding the state y, the
+// accumulated derivative and the stage input in registers beside the
+// transform and its twiddles does not fit the 256 registers a lane has at two
+// wavefronts per SIMD.  Here only the stage input u_s lives in registers
+// across the two transforms of a stage; y is read from and written back to
+// the caller's state in place, and the accumulated derivative sits in the
+// class workspace (one complex value per mode).  Every access is coalesced
+// (lanes own consecutive modes) and the per-instance vectors (256 KiB in
+// FP64) stay in L2 / MALL, so the traffic they add is on-chip.
+//
+// Per RK4 stage s (Sec. 2; stage times t, t+h/2, t+h/2, t+h): a = IDFT(u_s),
+// b = |a|^2 a, NK = DFT(b) (Eq. (4), the 1/N folded into g0/N), then
+//   k_s = (-kappa/2 + i(omega' - sigma(t_s))) u_s + i (g0/N) NK + [mu = 0] pump,
+//   acc = k_1 (s = 1), acc += 2 k_s (s = 2, 3), and the next stage input
+//   u_{s+1} = y + c_{s+1} h k_s, or at s = 4 the update y += h/6 (acc + k_4).
+#include "cme_lean.hpp"
+#include "cme_wave.hpp"
+
+namespace cme {
+
+// The two-level transform of cme_fft.hpp (fft_fwdpath / fft_backpath, one
+// element of the cross-wave DFT per lane and slot: Q = 1) with only the
+// sub-transform twiddles held in registers.  The cross-wave twiddles are
+// formed where they are applied:
+//   forward path  w^{n1 r}, r < WV, as powers of w^{n1} (n1 = l + 64 w);
+//   back path     w^{(l + 64 j)(w V + v)} = w^{l (w V + v)} (w^{64 (w V + v)})^j
+// (w = e^{-2 pi i / N}, conjugated for the inverse sign by ctw), from five
+// table entries per thread.
+template <int N, int E, int V, typename Real> struct StreamTw {
+  using WP = WavePlan<N, E, V, 0>;
+  cx<Real> sub[WP::Sub::NTW];
+  cx<Real> bx;     // w^{n1}
+  cx<Real> cy[V];  // w^{l (w V + v)}
+  cx<Real> dy[V];  // w^{64 (w V + v)}
+};
+
+template <int N, int E, int V, typename Real>
+__device__ __forceinline__ void load_stream_twiddles(StreamTw<N, E, V, Real> &tw,
+                                                     const cx<Real> *__restrict__ tab, int w,
+                                                     int l) {
+  using WP = WavePlan<N, E, V, 0>;
+  static_assert(WP::Q == 1, "one cross-wave element per slot");
+  load_twiddles<WP::N1, WP::ES, WP::WV>(tw.sub, tab, l);
+  tw.bx = tab[l + 64 * w];
+  sfor<0, V>([&](auto vi) {
+    constexpr int vv = decltype(vi)::value;
+    tw.cy[vv] = tab[(l * (w * V + vv)) & (N - 1)];
+    tw.dy[vv] = tab[(64 * (w * V + vv)) & (N - 1)];
+  });
+}
+
+template <int N, int E, int V, int S, int PS, bool PRE, typename Real>
+__device__ __forceinline__ void stream_fwdpath(cx<Real> (&v)[E], cx<Real> *X,
+                                               const StreamTw<N, E, V, Real> &tw, int w, int l) {
+  using WP = WavePlan<N, E, V, 0>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, ES = WP::ES;
+  if constexpr (PRE) cross_sync<WP::W>();
+  {
+    cx<Real> z[WV];
+    sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[decltype(ri)::value]; });
+    dft_reg<WV, S>(z);
+    cx<Real> t[WV];
+    pow_fill<WV>(t, tw.bx);
+    const int n1 = l + 64 * w;
+    sfor<0, WV>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      X[r * LB1 + lpad<PS>(n1)] = r == 0 ? z[0] : ctw<S>(z[r], t[r]);
+    });
+  }
+  cross_sync<WP::W>();
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    constexpr int vv = m / ES, j = m % ES;
+    v[m] = X[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)];
+  });
+  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+}
+
+template <int N, int E, int V, int S, int PS, typename Real>
+__device__ __forceinline__ void stream_backpath(cx<Real> (&v)[E], cx<Real> *X, cx<Real> *Y,
+                                                const StreamTw<N, E, V, Real> &tw, int w,
+                                                int l) {
+  using WP = WavePlan<N, E, V, 0>;
+  constexpr int LB1 = LdsLen<WP::N1, PS>::value;
+  constexpr int WV = WP::WV, ES = WP::ES;
+  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  if (Y == X) wave_sync();  // own regions: the transform's last reads come first
+  sfor<0, V>([&](auto vi) {
+    constexpr int vv = decltype(vi)::value;
+    cx<Real> dp[ES];
+    pow_fill<ES>(dp, tw.dy[vv]);
+    sfor<0, ES>([&](auto ji) {
+      constexpr int j = decltype(ji)::value;
+      constexpr int m = vv * ES + j;
+      const cx<Real> t = j == 0 ? tw.cy[vv] : cmul(tw.cy[vv], dp[j]);
+      Y[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)] = ctw<S>(v[m], t);
+    });
+  });
+  cross_sync<WP::W>();
+  const int n1 = l + 64 * w;
+  cx<Real> z[WV];
+  sfor<0, WV>([&](auto ri) {
+    constexpr int r = decltype(ri)::value;
+    z[r] = Y[r * LB1 + lpad<PS>(n1)];
+  });
+  dft_reg<WV, S>(z);
+  sfor<0, WV>([&](auto ri) { v[decltype(ri)::value] = z[decltype(ri)::value]; });
+}
+
+// Raw buffer accesses: one 32-bit per-lane offset register plus a constant
+// per-slot offset in a scalar register, so that the addresses of the E slots
+// a thread owns cost no 64-bit registers (hoisted out of the time loop, 64-bit
+// pointers for every slot and array would crowd out the transform).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, 0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, int vo, int so) {
+  if constexpr (sizeof(T) == 16)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0));
+  else if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+template <typename T>
+__device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo, int so) {
+  if constexpr (sizeof(T) == 16) {
+    using V4 = __attribute__((ext_vector_type(4))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(V4, x), r, vo, so, 0);
+  } else {
+    using V2 = __attribute__((ext_vector_type(2))) unsigned int;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, x), r, vo, so, 0);
+  }
+}
+
+// CH: the stage arithmetic runs in groups of CH slots with a scheduling
+// barrier between groups, which bounds how many of its loads are in flight
+// (and so the registers they hold) beside the transform's.
+template <typename Real, int N, int E, int V, int PS, int CH>
+__global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
+    rk4_stream(RunArgs a) {
+  constexpr int TP = 0;
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  using WP = WavePlan<N, E, V, TP>;
+  static_assert(WP::W > 1 && SH::IPB == 1, "one instance per workgroup");
+  __shared__ cx<Real> lds[SH::PER_INST];
+
+  const int lane = (int)threadIdx.x & 63;
+  const int w = (int)threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x;
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  cx<Real> *X = lds;
+  cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;  // FP32: a second exchange buffer fits
+  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + d.offset;
+  constexpr int CB = (int)sizeof(cx<Real>);
+  const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A, N * CB);
+  cx<Real> *work = reinterpret_cast<cx<Real> *>(a.work) + (int64_t)slot * 2 * N;
+  const __amdgpu_buffer_rsrc_t rACC = buf_rsrc(work, N * CB);
+  const __amdgpu_buffer_rsrc_t rU = buf_rsrc(work + N, N * CB);
+  const __amdgpu_buffer_rsrc_t rK = buf_rsrc(a.kappa + d.offset, N * 8);
+  const __amdgpu_buffer_rsrc_t rW = buf_rsrc(a.omega + d.offset, N * 8);
+  // slot m of this thread holds mode i0 + N1 m (Q = 1)
+  static_assert(WP::Q == 1, "one cross-wave element per slot");
+  const int i0 = lane + 64 * w;
+
+  StreamTw<N, E, V, Real> tw;
+  load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+
+  cx<Real> v[E];
+  const bool pump_owner = (w == 0 && lane == 0);  // mode N/2 sits in slot E/2 there
+  const Real gn = (Real)d.g0n;
+  const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
+  const double h = a.h;
+  const Real h2 = (Real)(0.5 * h), h1 = (Real)h, h6 = (Real)(h / 6.0), two = (Real)2;
+  cx<Real> *ckpt = reinterpret_cast<cx<Real> *>(a.ckpt);
+  int32_t to_ckpt = a.ckpt_every;
+  int64_t ckpt_slot = 0;
+  bool bad = false;
+
+  for (int64_t n = 0; n < a.n_steps; ++n) {
+    const double t0 = (double)(a.step0 + n) * h;
+    sfor<0, 4>([&](auto si) {
+      constexpr int s = decltype(si)::value;
+      // the stage input u_s: the state itself at the first stage, else U
+      const __amdgpu_buffer_rsrc_t rIn = s == 0 ? rA : rU;
+      const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        v[m] = buf_load<cx<Real>>(rIn, CB * i0, CB * WP::N1 * m);
+      });
+      // with one buffer the forward path fences the previous back path's reads
+      stream_fwdpath<N, E, V, +1, PS, !SH::TWO>(v, X, tw, w, lane);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
+        v[m] = {p * v[m].re, p * v[m].im};
+      });
+      stream_backpath<N, E, V, -1, PS>(v, X, Y, tw, w, lane);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        if constexpr (m % CH == 0) __builtin_amdgcn_sched_barrier(0);
+        constexpr int off = CB * WP::N1 * m;  // slot m: mode i0 + N1 m
+        const cx<Real> u = buf_load<cx<Real>>(rIn, CB * i0, off);
+        const Real lr = (Real)(-0.5 * buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m));
+        const Real det = (Real)(buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m) - sig);
+        cx<Real> k = {lr * u.re - det * u.im - gn * v[m].im, lr * u.im + det * u.re + gn * v[m].re};
+        if constexpr (m == E / 2) {
+          if (pump_owner) k = cadd(k, pump);
+        }
+        if constexpr (s == 0) {
+          buf_store(k, rACC, CB * i0, off);
+          buf_store(cx<Real>{u.re + h2 * k.re, u.im + h2 * k.im}, rU, CB * i0, off);  // u_1 = y
+        } else if constexpr (s < 3) {
+          const cx<Real> acc = buf_load<cx<Real>>(rACC, CB * i0, off);
+          buf_store(cx<Real>{acc.re + two * k.re, acc.im + two * k.im}, rACC, CB * i0, off);
+          const cx<Real> y = buf_load<cx<Real>>(rA, CB * i0, off);
+          const Real c = s == 1 ? h2 : h1;
+          buf_store(cx<Real>{y.re + c * k.re, y.im + c * k.im}, rU, CB * i0, off);
+        } else {
+          const cx<Real> acc = buf_load<cx<Real>>(rACC, CB * i0, off);
+          const cx<Real> y = buf_load<cx<Real>>(rA, CB * i0, off);
+          const cx<Real> tot = {acc.re + k.re, acc.im + k.im};
+          const cx<Real> yn = {y.re + h6 * tot.re, y.im + h6 * tot.im};
+          buf_store(yn, rA, CB * i0, off);
+          if (ckpt != nullptr && to_ckpt == 1)
+            ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = yn;
+          if (n + 1 == a.n_steps) bad |= !(isfinite(yn.re) && isfinite(yn.im));
+        }
+      });
+    });
+    if (ckpt != nullptr && --to_ckpt == 0) {
+      to_ckpt = a.ckpt_every;
+      ++ckpt_slot;
+    }
+  }
+  if (bad) atomicOr(&a.flags[id], 1);
+}
+
+template <typename Real, int N, int E, int V, int PS, int CH>
+hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
+  using SH = WaveShape<Real, N, E, V, PS, 0>;
+  if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
+  if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, CH>), dim3(a.count), dim3(SH::THREADS), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+// kind 13; two complex values of class workspace per mode (the accumulated
+// derivative and the stage input); no reverse sweep (the adjoint uses another
+// variant of the size)
+// (the tuning field holds CH)
+template <typename Real, int N, int E, int V, int PS, int CH> constexpr Variant stream_variant() {
+  using SH = WaveShape<Real, N, E, V, PS, 0>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, CH, 13, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES, &launch_stream_fwd<Real, N, E, V, PS, CH>, nullptr,
+                 2};
+}
+
+static const Variant kStreamVariants[] = {
+    stream_variant<double, 8192, 16, 2, 3, 2>(),
+    stream_variant<double, 8192, 16, 2, 3, 16>(),
+    stream_variant<float, 8192, 16, 2, 3, 16>(),
+    stream_variant<float, 8192, 16, 2, 3, 4>(),
+};
+
+const Variant *variants_stream(int *count) {
+  *count = (int)(sizeof(kStreamVariants) / sizeof(kStreamVariants[0]));
+  return kStreamVariants;
+}
+
+}  // namespace cme

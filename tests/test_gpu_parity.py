@@ -19,7 +19,7 @@ FP64_TOL = 1e-10
 
 # kernel kinds that step classic RK4 with the cyclic sum (the others: split-step,
 # padded sum, interaction-picture RK4, tested in their own files)
-RK4_KINDS = (0, 1, 2, 3, 6)
+RK4_KINDS = (0, 1, 2, 3, 6, 13)
 
 
 @pytest.fixture(scope="module")
