@@ -233,3 +233,26 @@ def test_cw_state_solves_the_single_mode_balance():
         # stationarity of dA/dt = (-1/2 - i sigma) A + sqrt(0.5) A_in + i |A|^2 A
         res = (-0.5 - 1j * sigma) * A + np.sqrt(0.5) * a_in + 1j * abs(A) ** 2 * A
         assert abs(res) < 1e-14
+
+
+def test_one_hip_runtime_after_load():
+    """load_library() imports torch before it opens libcme.so, so the HIP
+    runtime libcme.so needs resolves to the one torch already mapped: a second
+    libamdhip64 in the process (device pointers and streams of one runtime
+    handed to the other) crashed a GPU run once.  Checked in a fresh process
+    from /proc/self/maps."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_1307_3428_amd import cme\n"
+        "cme.load_library()\n"
+        "paths = set()\n"
+        "for line in open('/proc/self/maps'):\n"
+        "    f = line.split()\n"
+        "    if len(f) >= 6 and 'libamdhip64' in f[5]:\n"
+        "        paths.add(f[5])\n"
+        "print(len(paths), sorted(paths))\n")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.split()[0] == "1", r.stdout
