@@ -181,19 +181,32 @@ const Variant *default_variant(int precision, int n, int integrator) {
   return nullptr;
 }
 
-// FP64 classic RK4 at N = 8192: the LDS-resident kernel spills and is held
-// to one instance per CU, so up to ~160 instances the staged kernels, which
-// spread each instance over many CUs, are faster (106 vs 134 us per step at
-// 128 instances; 219 vs 145 at 256); this is the default for such classes.
+// Classic RK4 (cyclic sum) at N = 8192, by measured crossover (us per step
+// for the whole class):
+//   FP64: the staged kernels spread each instance over many CUs and win
+//   for small classes (four-wave workgroups: 39.7 at 1 instance, 70.5 at
+//   64); rk4_stream, one instance per CU with the state in global memory,
+//   above (59.7 at 1, 68.2 at 100, 71.8 at 128, 102.9 at 256; staged 96.8,
+//   111.5, 205.2);
+//   FP32: the one-transform wave kernel for small classes (38.1 at 1, 40.1
+//   at 64), rk4_stream above (45.1 at 1, 47.1 at 100, 48.5 at 128; wave
+//   61.0, 66.6).
 const Variant *class_default(int precision, int n, int integrator, size_t count) {
   const Variant *v = default_variant(precision, n, integrator);
-  if (precision == CME_F64 && n == 8192 && integrator == CME_RK4 && count <= 160) {
-    int cnt = 0;
-    const Variant *all = all_variants(&cnt);
+  if (n != 8192 || integrator != CME_RK4) return v;
+  int cnt = 0;
+  const Variant *all = all_variants(&cnt);
+  auto find = [&](int kind, int threads) -> const Variant * {
     for (int i = 0; i < cnt; ++i)
-      if (all[i].precision == precision && all[i].n == n && all[i].kind == 6) return &all[i];
-  }
-  return v;
+      if (all[i].precision == precision && all[i].n == n && all[i].kind == kind &&
+          (threads == 0 || all[i].threads == threads))
+        return &all[i];
+    return nullptr;
+  };
+  const Variant *pick = nullptr;
+  if (precision == CME_F64) pick = count <= 48 ? find(6, 256) : find(13, 0);
+  else if (count > 80) pick = find(13, 0);
+  return pick ? pick : v;
 }
 
 // compiled variants for a precision and size; integrator < 0: any

@@ -138,13 +138,13 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo,
   }
 }
 
-// CH: the stage arithmetic runs in groups of CH slots with a scheduling
-// barrier between groups, which bounds how many of its loads are in flight
-// (and so the registers they hold) beside the transform's.
-template <typename Real, int N, int E, int V, int PS, int CH>
+// D: prefetch distance of the stage arithmetic (slots whose operands are in
+// flight while one slot is computed).
+template <typename Real, int N, int E, int V, int PS, int D>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4_stream(RunArgs a) {
   constexpr int TP = 0;
+  static_assert(D >= 1, "prefetch distance");
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   using WP = WavePlan<N, E, V, TP>;
   static_assert(WP::W > 1 && SH::IPB == 1, "one instance per workgroup");
@@ -183,17 +183,18 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   int64_t ckpt_slot = 0;
   bool bad = false;
 
+  // the first stage input: the state
+  sfor<0, E>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
+  });
   for (int64_t n = 0; n < a.n_steps; ++n) {
     const double t0 = (double)(a.step0 + n) * h;
     sfor<0, 4>([&](auto si) {
       constexpr int s = decltype(si)::value;
-      // the stage input u_s: the state itself at the first stage, else U
+      // the stage input u_s is in v; a copy sits in the state (s = 0) or U
       const __amdgpu_buffer_rsrc_t rIn = s == 0 ? rA : rU;
       const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
-      sfor<0, E>([&](auto mi) {
-        constexpr int m = decltype(mi)::value;
-        v[m] = buf_load<cx<Real>>(rIn, CB * i0, CB * WP::N1 * m);
-      });
       // with one buffer the forward path fences the previous back path's reads
       stream_fwdpath<N, E, V, +1, PS, !SH::TWO>(v, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
@@ -202,37 +203,61 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
         v[m] = {p * v[m].re, p * v[m].im};
       });
       stream_backpath<N, E, V, -1, PS>(v, X, Y, tw, w, lane);
+      // Stage arithmetic, slot by slot, with the loads of slot m + D issued
+      // before slot m is computed (a ring of D slots of operands), so that
+      // the global-memory latency is paid about once per stage.  v[m] is
+      // consumed (N K) and refilled with the next stage input.
+      struct Ops {
+        cx<Real> u, acc, y;
+        double kap, om;
+      };
+      Ops ring[D];
+      __builtin_amdgcn_sched_barrier(0);  // no operand load above the transforms
+      auto fetch = [&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        constexpr int off = CB * WP::N1 * m;  // slot m: mode i0 + N1 m
+        Ops &o = ring[m % D];
+        o.u = buf_load<cx<Real>>(rIn, CB * i0, off);
+        o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
+        o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
+        if constexpr (s > 0) {
+          o.acc = buf_load<cx<Real>>(rACC, CB * i0, off);
+          o.y = buf_load<cx<Real>>(rA, CB * i0, off);
+        }
+      };
+      sfor<0, (D < E ? D : E)>(fetch);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
-        if constexpr (m % CH == 0) __builtin_amdgcn_sched_barrier(0);
-        constexpr int off = CB * WP::N1 * m;  // slot m: mode i0 + N1 m
-        const cx<Real> u = buf_load<cx<Real>>(rIn, CB * i0, off);
-        const Real lr = (Real)(-0.5 * buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m));
-        const Real det = (Real)(buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m) - sig);
+        __builtin_amdgcn_sched_barrier(0);
+        const Ops o = ring[m % D];
+        if constexpr (m + D < E) fetch(ic<m + D>{});
+        constexpr int off = CB * WP::N1 * m;
+        const Real lr = (Real)(-0.5 * o.kap);
+        const Real det = (Real)(o.om - sig);
+        const cx<Real> u = o.u;
         cx<Real> k = {lr * u.re - det * u.im - gn * v[m].im, lr * u.im + det * u.re + gn * v[m].re};
         if constexpr (m == E / 2) {
           if (pump_owner) k = cadd(k, pump);
         }
         if constexpr (s == 0) {
           buf_store(k, rACC, CB * i0, off);
-          buf_store(cx<Real>{u.re + h2 * k.re, u.im + h2 * k.im}, rU, CB * i0, off);  // u_1 = y
+          v[m] = {u.re + h2 * k.re, u.im + h2 * k.im};  // u_2, with y = u_1
+          buf_store(v[m], rU, CB * i0, off);
         } else if constexpr (s < 3) {
-          const cx<Real> acc = buf_load<cx<Real>>(rACC, CB * i0, off);
-          buf_store(cx<Real>{acc.re + two * k.re, acc.im + two * k.im}, rACC, CB * i0, off);
-          const cx<Real> y = buf_load<cx<Real>>(rA, CB * i0, off);
+          buf_store(cx<Real>{o.acc.re + two * k.re, o.acc.im + two * k.im}, rACC, CB * i0, off);
           const Real c = s == 1 ? h2 : h1;
-          buf_store(cx<Real>{y.re + c * k.re, y.im + c * k.im}, rU, CB * i0, off);
+          v[m] = {o.y.re + c * k.re, o.y.im + c * k.im};
+          buf_store(v[m], rU, CB * i0, off);
         } else {
-          const cx<Real> acc = buf_load<cx<Real>>(rACC, CB * i0, off);
-          const cx<Real> y = buf_load<cx<Real>>(rA, CB * i0, off);
-          const cx<Real> tot = {acc.re + k.re, acc.im + k.im};
-          const cx<Real> yn = {y.re + h6 * tot.re, y.im + h6 * tot.im};
-          buf_store(yn, rA, CB * i0, off);
+          const cx<Real> tot = {o.acc.re + k.re, o.acc.im + k.im};
+          v[m] = {o.y.re + h6 * tot.re, o.y.im + h6 * tot.im};
+          buf_store(v[m], rA, CB * i0, off);
           if (ckpt != nullptr && to_ckpt == 1)
-            ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = yn;
-          if (n + 1 == a.n_steps) bad |= !(isfinite(yn.re) && isfinite(yn.im));
+            ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = v[m];
+          if (n + 1 == a.n_steps) bad |= !(isfinite(v[m].re) && isfinite(v[m].im));
         }
       });
+      __builtin_amdgcn_sched_barrier(0);
     });
     if (ckpt != nullptr && --to_ckpt == 0) {
       to_ckpt = a.ckpt_every;
@@ -242,12 +267,12 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS, int CH>
+template <typename Real, int N, int E, int V, int PS, int D>
 hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
   if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, CH>), dim3(a.count), dim3(SH::THREADS), 0,
+  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D>), dim3(a.count), dim3(SH::THREADS), 0,
                      st, a);
   return hipGetLastError();
 }
@@ -255,19 +280,22 @@ hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
 // kind 13; two complex values of class workspace per mode (the accumulated
 // derivative and the stage input); no reverse sweep (the adjoint uses another
 // variant of the size)
-// (the tuning field holds CH)
-template <typename Real, int N, int E, int V, int PS, int CH> constexpr Variant stream_variant() {
+// (the tuning field holds D)
+template <typename Real, int N, int E, int V, int PS, int D> constexpr Variant stream_variant() {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, CH, 13, SH::IPB,
-                 SH::THREADS, SH::LDS_BYTES, &launch_stream_fwd<Real, N, E, V, PS, CH>, nullptr,
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D, 13, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES, &launch_stream_fwd<Real, N, E, V, PS, D>, nullptr,
                  2};
 }
 
+// The first of each precision is the default (measured, us per step for 128
+// instances: FP64 D = 2 71.8, D = 1 72.5, D = 4 78.6, D = 8 92.1 (larger
+// rings spill); FP32 D = 4 48.5, D = 8 48.7).
 static const Variant kStreamVariants[] = {
     stream_variant<double, 8192, 16, 2, 3, 2>(),
-    stream_variant<double, 8192, 16, 2, 3, 16>(),
-    stream_variant<float, 8192, 16, 2, 3, 16>(),
+    stream_variant<double, 8192, 16, 2, 3, 1>(),
     stream_variant<float, 8192, 16, 2, 3, 4>(),
+    stream_variant<float, 8192, 16, 2, 3, 8>(),
 };
 
 const Variant *variants_stream(int *count) {
