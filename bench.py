@@ -89,6 +89,52 @@ def counted_flops_per_step(n: int) -> float:
     return 8 * 5.0 * n * math.log2(n)
 
 
+def spectrum_errors(y, ref):
+    """Relative L2 errors of one instance's spectrum (centred order, pump mode
+    mu = 0 at N/2): the whole vector, the sidebands mu != 0 alone, the power
+    spectrum |A|^2 and its sidebands; and the share of ||ref|| the sidebands
+    hold.  The pump mode dominates ||A|| on the CW + noise workloads, so the
+    sideband figures are the ones that constrain the comb."""
+    import numpy as np
+    y = np.asarray(y, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    m = np.ones(ref.shape[0], bool)
+    m[ref.shape[0] // 2] = False
+
+    def rel(d, r):
+        nr = float(np.linalg.norm(r))
+        return float(np.linalg.norm(d)) / nr if nr > 0 else 0.0
+
+    py, pr = np.abs(y) ** 2, np.abs(ref) ** 2
+    return {"whole": rel(y - ref, ref), "side": rel((y - ref)[m], ref[m]),
+            "power": rel(py - pr, pr), "power_side": rel((py - pr)[m], pr[m]),
+            "side_frac": rel(ref[m], ref)}
+
+
+def golden(name: str):
+    """Stored oracle states (written by tests/golden/make_oracle_goldens.py,
+    which runs only the CPU oracle), or None."""
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    d = np.load(path, allow_pickle=False)
+    out = {k: d[k] for k in d.files if k != "meta"}
+    out["meta"] = json.loads(str(d["meta"]))
+    return out
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,7 +142,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed full runs")
     ap.add_argument("--rk-steps", type=int, default=None,
                     help="RK4 steps per run (default: the workload's 5e4)")
-    ap.add_argument("--parity-steps", type=int, default=100)
+    ap.add_argument("--parity-steps", type=int, default=250,
+                    help="RK4 steps of the live oracle sample (also the CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip adjoint / single-instance legs")
     ap.add_argument("--no-autotune", action="store_true")
@@ -108,6 +155,12 @@ def main() -> int:
     ap.add_argument("--staged-case", type=int, default=0, metavar="N",
                     help="only run the staged kernel on the staged leg's batch of size N "
                          "(8192, 16384 or 65536) for --rk-steps steps (profiling) and exit")
+    ap.add_argument("--profile-case", default="", metavar="N,B,KIND,PREC",
+                    help="only run B seeded random instances of N modes on the first kernel "
+                         "variant of that kind and precision (0 FP64, 1 FP32) for --rk-steps "
+                         "steps (profiling) and exit")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only run the uneven-octave leg (profiling) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -147,6 +200,24 @@ def main() -> int:
                                     steps=args.rk_steps or 20)))
         return 0
 
+    if args.profile_case:
+        n, b, kind, prec = (int(x) for x in args.profile_case.split(","))
+        kid = next(k for k in C.cme_list_kernels(prec, n) if C.cme_kernel_info(k)["kind"] == kind)
+        p = W.pack(W.random_batch(43, [n] * b, noise=1e-3))
+        steps = args.rk_steps or 200
+        with C.Plan(p, 2e-4, precision=prec) as plan:
+            plan.select(n, kid)
+            A = plan.state(p.a0)
+            s = timed_run(plan, A, steps, torch)
+            print(json.dumps({"case": args.profile_case, "kernel": plan.kernel(n)["name"],
+                              "us_per_step": 1e6 * s / steps,
+                              "mode_steps_per_s": p.total * steps / s}))
+        return 0
+
+    if args.uneven_only:
+        print(json.dumps(uneven_leg(C, W, torch)))
+        return 0
+
     rk_steps = args.rk_steps or 50000
     wl = W.sweep_n2048(n_steps=rk_steps)
     p = W.pack(wl.instances)
@@ -159,33 +230,62 @@ def main() -> int:
     kinfo = plan.kernel(n_modes)
     A0 = plan.state(p.a0)
 
-    # ---- parity on a sample, same launch configuration (all 256 instances) ----
+    # ---- parity at the full horizon against the stored oracle states, on the
+    # launch the bench times (all 256 instances, one run from A(0)) ----
+    horizon = None
+    g2 = golden("c2_sweep")
+    A = A0.clone()
+    plan.run(A, rk_steps)
+    torch.cuda.synchronize()
+    if g2 is not None and int(g2["meta"]["n_steps"]) == rk_steps:
+        y = A.cpu().numpy()
+        rows = []
+        for j, i in enumerate(g2["meta"]["indices"]):
+            e = spectrum_errors(y[p.slice(i)], g2["states"][-1][j])
+            e.update({"instance": int(i), "sigma": float(p.sigma0[i]),
+                      "twin_separation": float(g2["sep_whole"][-1][j]),
+                      "twin_separation_side": float(g2["sep_side"][-1][j])})
+            rows.append(e)
+        horizon = {"rk4_steps": rk_steps, "instances": rows,
+                   "max_rel_l2_err": max(r["whole"] for r in rows),
+                   "max_sideband_err": max(r["side"] for r in rows),
+                   "tolerance": 1e-10,
+                   "ok": max(r["whole"] for r in rows) <= 1e-10,
+                   "reference": "oracle states stored by tests/golden/make_oracle_goldens.py "
+                                "(CPU oracle only); twin_separation: the oracle's own spread "
+                                "after perturbing A(0) by 1e-12"}
+
+    # ---- live oracle sample on the same launch configuration (short horizon);
+    # its timing is the CPU baseline: at least as many instances as threads,
+    # so every thread runs one instance ----
     parity, cpu_s, threads, sub, pick = None, None, None, None, []
     if args.parity_steps > 0:
         import oracle
-        pick = [0, 32, 64, 96, 128, 160, 192, 224, 255][: max(1, min(9, p.batch))]
+        threads = oracle.max_threads()
+        n_pick = min(p.batch, max(16, threads))
+        pick = sorted({round(k * (p.batch - 1) / (n_pick - 1)) for k in range(n_pick)})
         A = A0.clone()
         plan.run(A, args.parity_steps)
         torch.cuda.synchronize()
         y = A.cpu().numpy()
         sub = W.pack([wl.instances[i] for i in pick])
-        threads = oracle.max_threads()
         t0 = time.perf_counter()
         ref, _ = oracle.run(sub, wl.h, args.parity_steps)
         cpu_s = time.perf_counter() - t0
-        errs = []
-        for j, i in enumerate(pick):
-            a, b = y[p.slice(i)], ref[sub.slice(j)]
-            errs.append(float(np.linalg.norm(a - b) / np.linalg.norm(b)))
-        # the same oracle on one core: one instance, 10 steps
+        errs = [spectrum_errors(y[p.slice(i)], ref[sub.slice(j)]) for j, i in enumerate(pick)]
+        # the same oracle on one core: one instance
         one = W.pack([wl.instances[pick[0]]])
+        one_steps = max(10, args.parity_steps // 4)
         oracle.set_threads(1)
         t1 = time.perf_counter()
-        oracle.run(one, wl.h, 10)
+        oracle.run(one, wl.h, one_steps)
         cpu1_s = time.perf_counter() - t1
         oracle.set_threads(threads)
-        parity = {"max_rel_l2_err": max(errs), "instances": pick, "rk4_steps": args.parity_steps,
-                  "tolerance": 1e-10, "ok": max(errs) <= 1e-10}
+        parity = {"max_rel_l2_err": max(e["whole"] for e in errs),
+                  "max_sideband_err": max(e["side"] for e in errs),
+                  "max_power_err": max(e["power"] for e in errs),
+                  "instances": pick, "rk4_steps": args.parity_steps,
+                  "tolerance": 1e-10, "ok": max(e["whole"] for e in errs) <= 1e-10}
     flags_out = plan.status()
 
     # ---- timed runs ----
@@ -244,19 +344,25 @@ def main() -> int:
                     "FP64 vector peak",
         },
         "parity": parity,
+        "parity_full_horizon": horizon,
         "all_finite": bool(finite),
     }
     if not args.no_cpu_baseline and cpu_s is not None:
+        used = min(threads, len(pick))
         out["cpu_baseline"] = {
             "value": sub.total * args.parity_steps / cpu_s,
             "unit": "mode-steps/s",
-            "cores": threads,
+            "cores": used,
             "kind": "oracle",
-            "sample": f"{len(pick)} of the 256 N=2048 instances x {args.parity_steps} RK4 steps "
-                      f"(O(N^2) direct-sum FWM, FP64, OpenMP), {cpu_s:.1f} s",
-            "one_core": {"value": 2048 * 10 / cpu1_s, "cores": 1,
-                         "sample": f"1 instance x 10 RK4 steps, {cpu1_s:.2f} s"},
+            "sample": f"{len(pick)} of the 256 N=2048 instances x {args.parity_steps} RK4 steps, "
+                      f"one instance per thread (O(N^2) direct-sum FWM, FP64, OpenMP), "
+                      f"{cpu_s:.1f} s",
+            "cpu_model": cpu_model(),
+            "one_core": {"value": 2048 * one_steps / cpu1_s, "cores": 1,
+                         "sample": f"1 instance x {one_steps} RK4 steps, {cpu1_s:.1f} s"},
         }
+        if not args.no_extras:
+            out["cpu_baseline"]["scaling"] = scaling_sweep(C, W, torch, threads)
     plan.close()
 
     if not args.no_extras:
@@ -269,6 +375,43 @@ def main() -> int:
         out["staged"] = staged_leg(C, W, torch)
     print(json.dumps(out))
     return 0
+
+
+def scaling_sweep(C, W, torch, threads):
+    """Cost per mode-step against N (Sec. 2: the transform evaluation of the
+    four-wave-mixing sum is O(N log N) per right-hand side, the direct sum
+    O(N^2)): the CPU oracle (direct sum; one instance per thread) and the GPU
+    (256 instances of N modes, default kernels), N = 64 ... 8192, seeded
+    random parameters, classic RK4."""
+    import numpy as np
+    import oracle
+    rows = []
+    for n in (64, 128, 256, 512, 1024, 2048, 4096, 8192):
+        insts = W.random_batch(97, [n] * 256, noise=1e-3)
+        p = W.pack(insts)
+        gpu_steps = max(20, (1 << 24) // (256 * n))
+        with C.Plan(p, 1e-3) as plan:
+            A = plan.state(p.a0)
+            plan.run(A, 5)
+            torch.cuda.synchronize()
+            g = timed_run(plan, A, gpu_steps, torch)
+            kname = plan.kernel(n)["name"]
+        sub = W.pack(insts[:threads])
+        cpu_steps = max(1, int(3e8 / (64.0 * n * n)))
+        t0 = time.perf_counter()
+        oracle.run(sub, 1e-3, cpu_steps)
+        c = time.perf_counter() - t0
+        rows.append({"n": n, "gpu_mode_steps_per_s": p.total * gpu_steps / g,
+                     "oracle_mode_steps_per_s": sub.total * cpu_steps / c,
+                     "gpu_kernel": kname, "oracle_steps": cpu_steps})
+    for r in rows:
+        r["gpu_over_oracle"] = r["gpu_mode_steps_per_s"] / r["oracle_mode_steps_per_s"]
+    ns = np.log2([r["n"] for r in rows])
+    fit = lambda key: float(np.polyfit(ns, np.log2([1.0 / r[key] for r in rows]), 1)[0])
+    return {"workload": "256 random instances per N (GPU), one per thread (oracle), RK4 h=1e-3",
+            "rows": rows,
+            "slope_log2_time_per_mode_step_vs_log2_n": {"oracle": fit("oracle_mode_steps_per_s"),
+                                                         "gpu": fit("gpu_mode_steps_per_s")}}
 
 
 def adjoint_leg(C, W, torch):
@@ -337,23 +480,76 @@ def rk4_stable(inst, h):
 
 def uneven_leg(C, W, torch, steps=20000):
     """The uneven-octave batch, FP64 and FP32, one plan per precision (size
-    classes launched concurrently), on the classically RK4-stable instances."""
+    classes launched concurrently), on the classically RK4-stable instances.
+    Also: every instance's FP32 result against the GPU's FP64 result after
+    the full horizon (labelled as such), and the sampled instances against
+    the stored oracle states after 2e3 steps (all four classes) and 2e4 steps
+    (N <= 2048)."""
+    import numpy as np
     wl = W.uneven_octave(n_steps=steps)
-    keep = [x for x in wl.instances if rk4_stable(x, wl.h)]
+    keep_idx = [i for i, x in enumerate(wl.instances) if rk4_stable(x, wl.h)]
+    keep = [wl.instances[i] for i in keep_idx]
     p = W.pack(keep)
     out = {"workload": f"uneven_octave: {len(keep)} of {len(wl.instances)} instances "
                        f"(classic RK4 stable), N in {{1024,2048,4096,8192}}, {steps} steps",
            "excluded_unstable": len(wl.instances) - len(keep),
            "by_n": {str(n): int(sum(1 for x in keep if x.n_modes == n))
                     for n in (1024, 2048, 4096, 8192)}}
+    g3 = golden("c3_uneven")
+    short = int(g3["meta"]["short"]) if g3 is not None else 2000
+    finals, shorts = {}, {}
     for prec, name in ((C.CME_F64, "fp64"), (C.CME_F32, "fp32")):
         with C.Plan(p, wl.h, precision=prec, flags=C.CME_INIT_AUTOTUNE) as plan:
             A = plan.state(p.a0)
-            plan.run(A, 200)
+            plan.run(A, short)
             torch.cuda.synchronize()
+            shorts[name] = A.cpu().numpy().astype(np.complex128)
+            plan.run(A, steps - short, step0=short)
+            torch.cuda.synchronize()
+            finals[name] = A.cpu().numpy().astype(np.complex128)
+            A = plan.state(p.a0)
             s = timed_run(plan, A, steps, torch)
             out[name] = {"mode_steps_per_s": p.total * steps / s, "seconds": s,
+                         "all_finite": not bool(plan.status().any()),
                          "kernels": {str(n): plan.kernel(n)["name"] for n in (1024, 2048, 4096, 8192)}}
+    # FP32 against the GPU's FP64 run, every instance, full horizon
+    e32 = [spectrum_errors(finals["fp32"][p.slice(b)], finals["fp64"][p.slice(b)])
+           for b in range(p.batch)]
+    out["fp32_vs_gpu_fp64"] = {
+        "note": "FP32 GPU result against the FP64 GPU result (not the oracle) after "
+                f"{steps} steps, per instance in batch order (instance ids in 'ids')",
+        "ids": keep_idx,
+        "whole": [float("%.3g" % e["whole"]) for e in e32],
+        "side": [float("%.3g" % e["side"]) for e in e32],
+        "power": [float("%.3g" % e["power"]) for e in e32],
+        "max_whole": max(e["whole"] for e in e32),
+        "median_whole": float(np.median([e["whole"] for e in e32])),
+        "max_side": max(e["side"] for e in e32),
+        "median_side": float(np.median([e["side"] for e in e32])),
+    }
+    # both precisions against the stored oracle states
+    if g3 is not None and int(g3["meta"]["n_steps"]) == steps:
+        pos = {i: b for b, i in enumerate(keep_idx)}
+        ref_short, ref_full = g3["states_short"], g3["states_full"]
+        res = {}
+        for name in ("fp64", "fp32"):
+            rows, o = [], 0
+            for i in g3["meta"]["indices_short"]:
+                n = wl.instances[i].n_modes
+                e = spectrum_errors(shorts[name][p.slice(pos[i])], ref_short[o:o + n])
+                rows.append({"instance": i, "n": n, "steps": short, **e})
+                o += n
+            o = 0
+            for i in g3["meta"]["indices_full"]:
+                n = wl.instances[i].n_modes
+                e = spectrum_errors(finals[name][p.slice(pos[i])], ref_full[o:o + n])
+                rows.append({"instance": i, "n": n, "steps": steps, **e})
+                o += n
+            res[name] = {"max_whole": max(r["whole"] for r in rows),
+                         "max_side": max(r["side"] for r in rows),
+                         "rows": [{k: (float("%.3g" % v) if isinstance(v, float) else v)
+                                   for k, v in r.items()} for r in rows]}
+        out["vs_oracle"] = res
     # all 512 instances, the ones classic RK4 refuses included, with the
     # interaction-picture RK4 (the linear part integrated exactly)
     pa = W.pack(wl.instances)
@@ -361,6 +557,7 @@ def uneven_leg(C, W, torch, steps=20000):
         A = plan.state(pa.a0)
         plan.run(A, 200)
         torch.cuda.synchronize()
+        A = plan.state(pa.a0)
         s = timed_run(plan, A, steps, torch)
         out["fp64_rk4ip_all"] = {
             "instances": pa.batch, "mode_steps_per_s": pa.total * steps / s, "seconds": s,

@@ -349,6 +349,13 @@ def adjoint_n2048(n_steps: int = 5000, sigma: float = 6.0, config_id: int = 4,
                     extra={"target": target, "ckpt_every": 100})
 
 
+def adjoint_soliton_n2048(n_steps: int = 5000) -> Workload:
+    """Soliton-regime companion of adjoint_n2048: the same recipe at sigma = 3
+    (zeta = 3, inside the soliton existence range at 4x threshold), so the
+    seeded sech pulse is held rather than decaying."""
+    return adjoint_n2048(n_steps=n_steps, sigma=3.0, config_id=6)
+
+
 def fig1_ensemble(n_steps: Optional[int] = None, h: float = 1e-3, noise: float = 1e-6) -> Workload:
     """Parameters of the paper's Fig. 1: N = 256, normalised time 128 pi,
     Omega_mu = -0.00625 mu^2, kappa_mu = kappa_0, f0 in {1.01, 1.2, 1.8, 4} sqrt(2).
@@ -454,5 +461,6 @@ WORKLOADS = {
     "sweep_n2048": sweep_n2048,
     "uneven_octave": uneven_octave,
     "adjoint_n2048": adjoint_n2048,
+    "adjoint_soliton_n2048": adjoint_soliton_n2048,
     "fig1_ensemble": fig1_ensemble,
 }
