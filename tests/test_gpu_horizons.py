@@ -1,0 +1,305 @@
+"""GPU parity at each workload's own horizon, against oracle states stored in
+tests/golden/ by make_oracle_goldens.py (which runs only the CPU oracle).
+
+Every stored case also holds the oracle's two-trajectory test: the relative
+separation, at each stored horizon, between the reference run and a twin
+whose A(0) was moved by 1e-12.  A horizon is *insensitive* when that
+separation stays <= 1e-10 (the trajectory amplifies an input change by at
+most 100): there the GPU result, which differs from the oracle's only by
+rounding order, is held to the FP64 bar of 1e-10, on the whole spectrum and
+on the sidebands mu != 0 alone (the pump mode dominates ||A|| on these
+workloads).  Past that point a trajectory amplifies rounding differences
+like any other input change (modulation-instability growth, chaotic
+transients), so the bar there -- and at every later horizon of the same run,
+which keeps what that stretch amplified -- is that the GPU stays within an
+order of magnitude of the oracle's own spread (the twin separation).  The
+sidebands alone are held to the same bars, or to the rounding floor of
+sidebands that hold only a small share of ||A|| (see check).
+
+The runs use the launch configuration the benchmark times: the whole batch
+of the workload in one plan (all 256 sweep instances; the 485 uneven-octave
+instances classic RK4 is stable for, every size class launched together).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1307_3428_amd import workloads as W
+from parity_metrics import errors
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-4
+INSENSITIVE = 1e-10   # twin separation (from a 1e-12 change) up to which the bar applies
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load(case):
+    path = os.path.join(GOLDEN, f"oracle_{case}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated yet: python tests/golden/make_oracle_goldens.py {case}")
+    d = np.load(path, allow_pickle=False)
+    out = {k: d[k] for k in d.files if k != "meta"}
+    out["meta"] = json.loads(str(d["meta"]))
+    return out
+
+
+@pytest.fixture(scope="module")
+def cme():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1307_3428_amd import cme as C
+    C.load_library()
+    return C
+
+
+EPS = {FP64_TOL: 2.0 ** -53, FP32_TOL: 2.0 ** -24}   # unit roundoff of the precision held to tol
+
+
+SPREAD = 10.0   # sensitive horizons: within an order of magnitude of the twin's separation
+
+
+def check(label, y, ref, sep_whole, steps, tol=FP64_TOL, sep_side=None, after_sensitive=False):
+    """Assert the bar for one instance at one horizon; returns the errors.
+
+    Insensitive horizon: the whole spectrum <= tol, the sidebands alone
+    <= tol or the rounding floor of sidebands that hold a share f of ||A||
+    after n steps, eps sqrt(n) / f (eps the unit roundoff: every step rounds
+    at the scale of the pump mode, and a sideband cannot be resolved relative
+    to itself below that).
+    Sensitive horizon (twin separation > 1e-10 here, or at an earlier stored
+    horizon of the same run: what a sensitive stretch amplified stays in the
+    state after it): the whole spectrum and the sidebands within SPREAD times
+    the oracle's own spread under a 1e-12 change of A(0) (or the bars above,
+    if larger)."""
+    e = errors(y, ref)
+    sensitive = sep_whole > INSENSITIVE or after_sensitive
+    floor = EPS[tol] * np.sqrt(max(steps, 1)) / max(e["side_frac"], 1e-300)
+    whole_bar = max(tol, SPREAD * sep_whole) if sensitive else tol
+    side_bar = max(tol, floor)
+    if sensitive and sep_side is not None:
+        side_bar = max(side_bar, SPREAD * sep_side)
+    print(f"{label}: whole {e['whole']:.2e} (bar {whole_bar:.1e}) side {e['side']:.2e} "
+          f"(bar {side_bar:.1e}) power {e['power']:.2e} (sidebands hold {e['side_frac']:.1e} "
+          f"of ||A||; twin separation {sep_whole:.1e}{', sensitive' if sensitive else ''})",
+          flush=True)
+    assert e["whole"] <= whole_bar, (label, e, whole_bar)
+    assert e["side"] <= side_bar, (label, e, side_bar)
+    return e
+
+
+def run_with_ckpts(C, packed, h, steps, every, flags=0, precision=None, integrator=None):
+    import torch
+    kw = {}
+    if precision is not None:
+        kw["precision"] = precision
+    if integrator is not None:
+        kw["integrator"] = integrator
+    with C.Plan(packed, h, flags=flags, **kw) as plan:
+        A = plan.state(packed.a0)
+        ck = torch.zeros((steps // every, packed.total), dtype=A.dtype, device=A.device)
+        plan.run(A, steps, ckpt_every=every, ckpt=ck)
+        torch.cuda.synchronize()
+        st = plan.status()
+        return ck.cpu().numpy().astype(np.complex128), A.cpu().numpy().astype(np.complex128), st
+
+
+def test_soliton_ramp_n1024_full_horizon(cme):
+    """Single soliton run (N = 1024, sigma ramped -2 -> 8 over tau in [0, 200],
+    4e5 RK4 steps): every 4e4-step state against the oracle.  The ramp crosses
+    the modulation-instability window (tau ~ 33 ... 67), where the trajectory
+    is sensitive, and ends on the unique single-mode state (zeta = 16), which
+    contracts the spread again."""
+    g = load("c1_ramp")
+    wl = W.soliton_ramp_n1024()
+    p = W.pack(wl.instances)
+    every = int(g["steps"][0])
+    ck, yT, st = run_with_ckpts(cme, p, wl.h, wl.n_steps, every)
+    assert not st.any()
+    assert np.array_equal(ck[-1], yT)
+    seps = [float(x) for x in g["sep_whole"][:, 0]]
+    for j, step in enumerate(g["steps"]):
+        check(f"ramp step {step}", ck[j], g["states"][j], seps[j], int(step),
+              sep_side=float(g["sep_side"][j][0]),
+              after_sensitive=max(seps[:j + 1]) > INSENSITIVE)
+    # the end is the insensitive single-mode state: the full bar holds there
+    assert float(g["sep_whole"][-1][0]) <= INSENSITIVE
+
+
+def test_soliton_held_n1024(cme):
+    """Companion of the ramp: a soliton held at sigma = 1.5 (zeta = 3), 4e4 steps."""
+    g = load("c1s_held")
+    wl = W.soliton_held_n1024()
+    p = W.pack(wl.instances)
+    every = int(g["steps"][0])
+    ck, _, st = run_with_ckpts(cme, p, wl.h, wl.n_steps, every)
+    assert not st.any()
+    steps = list(g["steps"])
+    for j, step in enumerate(g["states_steps"]):
+        k = steps.index(step)
+        check(f"held step {step}", ck[k], g["states"][j], float(g["sep_whole"][k][0]), int(step),
+              sep_side=float(g["sep_side"][k][0]),
+              after_sensitive=float(g["sep_whole"][:k + 1, 0].max()) > INSENSITIVE)
+    # the soliton is really there: sidebands carry a large share of ||A||
+    assert errors(ck[-1], ck[-1])["side_frac"] > 0.1
+
+
+def test_sweep_n2048_full_horizon_full_launch(cme):
+    """The 256 x N = 2048 detuning sweep over its full 5e4 steps in one
+    launch (autotuned, as benchmarked); both detuning ends, two instances
+    inside the modulation-instability window and the middle of the sweep
+    against the oracle after 5e3 and 5e4 steps."""
+    g = load("c2_sweep")
+    wl = W.sweep_n2048()
+    p = W.pack(wl.instances)
+    every = int(g["steps"][0])
+    ck, _, st = run_with_ckpts(cme, p, wl.h, wl.n_steps, every, flags=cme.CME_INIT_AUTOTUNE)
+    assert not st.any()
+    steps = list(g["steps"])
+    for j, step in enumerate(g["states_steps"]):
+        k = steps.index(step)
+        for b, i in enumerate(g["meta"]["indices"]):
+            check(f"sweep instance {i} (sigma {p.sigma0[i]:+.3f}) step {step}",
+                  ck[k][p.slice(i)], g["states"][j][b], float(g["sep_whole"][k][b]), int(step),
+                  sep_side=float(g["sep_side"][k][b]),
+                  after_sensitive=float(g["sep_whole"][:k + 1, b].max()) > INSENSITIVE)
+
+
+def _uneven(C):
+    wl = W.uneven_octave()
+    g = load("c3_uneven")
+    keep = [i for i, x in enumerate(wl.instances) if rk4_stable(x, wl.h)]
+    return wl, g, keep
+
+
+def rk4_stable(inst, h):
+    ok = True
+    for sg in (inst.sigma0, inst.sigma1):
+        z = h * (-0.5 * inst.kappa + 1j * (inst.omega - sg))
+        ok &= bool(np.all(np.abs(1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24) <= 1 + 1e-12))
+    return ok
+
+
+def _uneven_checks(C, precision, tol):
+    import torch
+    wl, g, keep = _uneven(C)
+    p = W.pack([wl.instances[i] for i in keep])
+    pos = {i: b for b, i in enumerate(keep)}
+    short = int(g["meta"]["short"])
+    with C.Plan(p, wl.h, precision=precision, flags=C.CME_INIT_AUTOTUNE) as plan:
+        for n in (1024, 2048, 4096, 8192):
+            print(f"N={n}: {plan.kernel(n)['name']}", flush=True)
+        A = plan.state(p.a0)
+        plan.run(A, short)
+        torch.cuda.synchronize()
+        y_short = A.cpu().numpy().astype(np.complex128)
+        plan.run(A, wl.n_steps - short, step0=short)
+        torch.cuda.synchronize()
+        y_full = A.cpu().numpy().astype(np.complex128)
+        assert not plan.status().any()
+    large_twin = set(g["meta"]["indices_large_twinned"])
+    small = g["meta"]["indices_full"]
+    rows, o = [], 0
+    for k, i in enumerate(g["meta"]["indices_short"]):
+        n = wl.instances[i].n_modes
+        ref = g["states_short"][o:o + n]
+        o += n
+        if i in small:
+            sep = float(g["sep_whole_small"][0][small.index(i)])
+            sep_s = float(g["sep_side_small"][0][small.index(i)])
+        elif i in large_twin:
+            sep = float(g["sep_whole_large"][g["meta"]["indices_large_twinned"].index(i)])
+            sep_s = float(g["sep_side_large"][g["meta"]["indices_large_twinned"].index(i)])
+        else:
+            sep, sep_s = 0.0, None   # no twin: held to the bar (a 2e3-step horizon, T = 0.4)
+        rows.append(check(f"uneven N={n} instance {i} step {short}", y_short[p.slice(pos[i])],
+                          ref, sep, short, tol, sep_side=sep_s))
+    o = 0
+    for k, i in enumerate(small):
+        n = wl.instances[i].n_modes
+        ref = g["states_full"][o:o + n]
+        o += n
+        rows.append(check(f"uneven N={n} instance {i} step {wl.n_steps}",
+                          y_full[p.slice(pos[i])], ref, float(g["sep_whole_small"][-1][k]),
+                          wl.n_steps, tol, sep_side=float(g["sep_side_small"][-1][k]),
+                          after_sensitive=float(g["sep_whole_small"][:, k].max()) > INSENSITIVE))
+    return rows
+
+
+def test_uneven_octave_fp64_full_batch(cme):
+    """The uneven-octave batch (485 instances, four size classes in one plan):
+    8 instances per class against the oracle after 2e3 steps, and the
+    N = 1024 and 2048 ones after the full 2e4."""
+    _uneven_checks(cme, cme.CME_F64, FP64_TOL)
+
+
+def test_uneven_octave_fp32_against_oracle(cme):
+    """The same batch in FP32 (FP64 only in the time bookkeeping) against the
+    FP64 oracle: relative L2 <= 1e-4 where the trajectory is insensitive.  The
+    sideband errors are reported: in FP32 they are set by the pump's rounding
+    (about 6e-8 of ||A||) over sidebands that hold as little as 1e-5 of it."""
+    rows = _uneven_checks(cme, cme.CME_F32, FP32_TOL)
+    print("fp32 max whole %.2e, max sideband %.2e" % (max(r["whole"] for r in rows),
+                                                      max(r["side"] for r in rows)))
+
+
+def test_uneven_octave_rk4ip_all_instances(cme):
+    """All 512 uneven-octave instances with the interaction-picture RK4 (the
+    27 classic RK4 refuses included), 2e3 steps, against the oracle's RK4IP."""
+    import torch
+    g = load("c3_uneven_ip")
+    wl = W.uneven_octave()
+    p = W.pack(wl.instances)
+    with cme.Plan(p, wl.h, integrator=cme.CME_RK4IP, flags=cme.CME_INIT_AUTOTUNE) as plan:
+        A = plan.state(p.a0)
+        plan.run(A, int(g["meta"]["n_steps"]))
+        torch.cuda.synchronize()
+        y = A.cpu().numpy()
+        assert not plan.status().any()
+    o = 0
+    for k, i in enumerate(g["meta"]["indices"]):
+        n = wl.instances[i].n_modes
+        check(f"rk4ip N={n} instance {i}{' (refused by RK4)' if i in g['meta']['rk4_unstable'] else ''}",
+              y[p.slice(i)], g["states"][o:o + n], float(g["sep_whole"][k]),
+              int(g["meta"]["n_steps"]), sep_side=float(g["sep_side"][k]))
+        o += n
+
+
+@pytest.mark.parametrize("case,make", [("c4_adjoint", "adjoint_n2048"),
+                                       ("c4s_adjoint", "adjoint_soliton_n2048")])
+def test_adjoint_workload_against_oracle_adjoint(cme, case, make):
+    """The gradient workload (N = 2048, 5000 steps, checkpoints every 100) and
+    its soliton-regime companion: the forward state, and cme_adjoint fed the
+    oracle's cotangent of L = sum (|A(T)|^2 - t)^2, against the oracle's
+    adjoint: <= 1e-10 relative on the cotangent of A(0), on dL/domega',
+    dL/dkappa and dL/dA_in."""
+    import torch
+    g = load(case)
+    wl = getattr(W, make)()
+    p = W.pack(wl.instances)
+    K = int(g["meta"]["ckpt_every"])
+    assert float(g["sep_whole"][-1]) <= INSENSITIVE
+    with cme.Plan(p, wl.h) as plan:
+        A0 = plan.state(p.a0)
+        ck = torch.zeros((wl.n_steps // K, p.total), dtype=A0.dtype, device=A0.device)
+        A = A0.clone()
+        plan.run(A, wl.n_steps, ckpt_every=K, ckpt=ck)
+        out = plan.adjoint(A0, plan.state(g["gT"]), wl.n_steps, ckpt_every=K, ckpt=ck)
+        torch.cuda.synchronize()
+        yT = A.cpu().numpy()
+        assert not plan.status().any()
+    check(f"{case} forward", yT, g["yT"], float(g["sep_whole"][-1]), wl.n_steps,
+          sep_side=float(g["sep_side"][-1]),
+          after_sensitive=float(g["sep_whole"].max()) > INSENSITIVE)
+    gain = out["g_ain"].cpu().numpy().reshape(-1, 2)
+    pairs = {"gA_0": (out["gA_0"].cpu().numpy(), g["gy0"]),
+             "g_omega": (out["g_omega"].cpu().numpy(), g["g_omega"]),
+             "g_kappa": (out["g_kappa"].cpu().numpy(), g["g_kappa"]),
+             "g_ain": (gain[:, 0] + 1j * gain[:, 1], g["g_ain"])}
+    for name, (got, ref) in pairs.items():
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        print(f"{case} {name}: {err:.2e}", flush=True)
+        assert err <= FP64_TOL, (name, err)
