@@ -172,6 +172,8 @@ def main() -> int:
                          "steps (profiling) and exit")
     ap.add_argument("--uneven-only", action="store_true",
                     help="only run the uneven-octave leg (profiling) and exit")
+    ap.add_argument("--single-only", action="store_true",
+                    help="only run the single-instance leg (profiling) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -227,6 +229,10 @@ def main() -> int:
 
     if args.uneven_only:
         print(json.dumps(uneven_leg(C, W, torch)))
+        return 0
+
+    if args.single_only:
+        print(json.dumps(single_leg(C, W, torch)))
         return 0
 
     rk_steps = args.rk_steps or 50000
