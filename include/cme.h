@@ -264,7 +264,8 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
  * twiddles are held in registers; kinds 6, 8, 9, 10: wavefronts per
- * workgroup; kind 13: slots per group of the stage arithmetic).
+ * workgroup; kind 13: operand prefetch distance of the stage arithmetic, + 16
+ * when the sub-transform twiddles are formed from one base per pass).
  * Returns 10, or CME_EINVAL. */
 int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 

@@ -186,10 +186,9 @@ const Variant *default_variant(int precision, int n, int integrator) {
 //   FP64: the staged kernels spread each instance over many CUs and win
 //   for small classes (four-wave workgroups: 39.7 at 1 instance, 70.5 at
 //   64); rk4_stream, one instance per CU with the state in global memory,
-//   above (59.7 at 1, 68.2 at 100, 71.8 at 128, 102.9 at 256; staged 96.8,
-//   111.5, 205.2);
+//   above (58.8 at 1, 65.6 at 100, 68.9 at 128; staged 96.8, 111.5);
 //   FP32: the one-transform wave kernel for small classes (38.1 at 1, 40.1
-//   at 64), rk4_stream above (45.1 at 1, 47.1 at 100, 48.5 at 128; wave
+//   at 64), rk4_stream above (44.9 at 1, 46.5 at 100, 47.0 at 128; wave
 //   61.0, 66.6).
 const Variant *class_default(int precision, int n, int integrator, size_t count) {
   const Variant *v = default_variant(precision, n, integrator);

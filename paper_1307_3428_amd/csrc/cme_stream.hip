@@ -24,27 +24,42 @@ namespace cme {
 
 // The two-level transform of cme_fft.hpp (fft_fwdpath / fft_backpath, one
 // element of the cross-wave DFT per lane and slot: Q = 1) with only the
-// sub-transform twiddles held in registers.  The cross-wave twiddles are
-// formed where they are applied:
+// sub-transform twiddles held in registers, all their powers or (PB) one
+// base per pass.  The cross-wave twiddles are formed where they are applied:
 //   forward path  w^{n1 r}, r < WV, as powers of w^{n1} (n1 = l + 64 w);
 //   back path     w^{(l + 64 j)(w V + v)} = w^{l (w V + v)} (w^{64 (w V + v)})^j
 // (w = e^{-2 pi i / N}, conjugated for the inverse sign by ctw), from five
 // table entries per thread.
-template <int N, int E, int V, typename Real> struct StreamTw {
+// PB: one base per pass, its powers formed in the pass (as in cme_lean.hpp):
+// 48 fewer registers for the FP64 kernel, which then does not spill.
+template <int N, int E, int V, bool PB, typename Real> struct StreamTw {
   using WP = WavePlan<N, E, V, 0>;
-  cx<Real> sub[WP::Sub::NTW];
+  cx<Real> sub[PB ? WP::Sub::P : WP::Sub::NTW];
   cx<Real> bx;     // w^{n1}
   cx<Real> cy[V];  // w^{l (w V + v)}
   cx<Real> dy[V];  // w^{64 (w V + v)}
 };
 
-template <int N, int E, int V, typename Real>
-__device__ __forceinline__ void load_stream_twiddles(StreamTw<N, E, V, Real> &tw,
+template <int N, int E, int V, bool PB, typename Real>
+__device__ __forceinline__ void load_stream_twiddles(StreamTw<N, E, V, PB, Real> &tw,
                                                      const cx<Real> *__restrict__ tab, int w,
                                                      int l) {
   using WP = WavePlan<N, E, V, 0>;
+  using PL = typename WP::Sub;
   static_assert(WP::Q == 1, "one cross-wave element per slot");
-  load_twiddles<WP::N1, WP::ES, WP::WV>(tw.sub, tab, l);
+  if constexpr (PB) {
+    // base of pass p: w_N1^{k STRIDE}, k = l mod NS_p (the sub-transform
+    // table is every WV-th entry of the length-N one)
+    sfor<1, PL::P>([&](auto pi) {
+      constexpr int p = decltype(pi)::value;
+      constexpr int R = PL::radix(p), NSp = PL::ns(p);
+      static_assert(PL::qd(p) == 1, "one twiddle set per pass");
+      constexpr int STRIDE = WP::N1 / (NSp * R);
+      tw.sub[p] = tab[(l & (NSp - 1)) * STRIDE * WP::WV];
+    });
+  } else {
+    load_twiddles<WP::N1, WP::ES, WP::WV>(tw.sub, tab, l);
+  }
   tw.bx = tab[l + 64 * w];
   sfor<0, V>([&](auto vi) {
     constexpr int vv = decltype(vi)::value;
@@ -53,9 +68,80 @@ __device__ __forceinline__ void load_stream_twiddles(StreamTw<N, E, V, Real> &tw
   });
 }
 
-template <int N, int E, int V, int S, int PS, bool PRE, typename Real>
+// fft_wave_multi (cme_fft.hpp) with the twiddles of each pass formed from
+// its base: V independent wave-local transforms of length N1 = 64 ES in the
+// regions reg + v LB1.
+template <int N1, int ES, int V, int S, int PS, typename Real>
+__device__ __forceinline__ void stream_wave_multi(cx<Real> (&v)[V * ES], cx<Real> *reg,
+                                                  const cx<Real> (&tb)[(FftPlan<N1, ES>::P)],
+                                                  int l) {
+  using PL = FftPlan<N1, ES>;
+  constexpr int T = 64;
+  constexpr int LB1 = LdsLen<N1, PS>::value;
+  sfor<0, PL::P>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), NSp = PL::ns(p);
+    constexpr int Qb = ES / R;
+    constexpr bool LAST = p == PL::P - 1;
+    if constexpr (p > 0) {
+      sfor<0, V>([&](auto vi) {
+        constexpr int vv = decltype(vi)::value;
+        sfor<0, ES>([&](auto mi) {
+          constexpr int m = decltype(mi)::value;
+          v[vv * ES + m] = reg[vv * LB1 + lpad<PS>(l + m * T)];
+        });
+      });
+    }
+    if constexpr (!LAST) wave_sync();  // in place: reads before writes
+    cx<Real> t[R];
+    if constexpr (NSp > 1) pow_fill<R>(t, tb[p]);
+    sfor<0, V>([&](auto vi) {
+      constexpr int vv = decltype(vi)::value;
+      sfor<0, Qb>([&](auto qi) {
+        constexpr int q = decltype(qi)::value;
+        cx<Real> z[R];
+        sfor<0, R>([&](auto ri) {
+          z[decltype(ri)::value] = v[vv * ES + q + decltype(ri)::value * Qb];
+        });
+        if constexpr (NSp > 1) {
+          sfor<1, R>([&](auto ri) {
+            constexpr int r = decltype(ri)::value;
+            z[r] = ctw<S>(z[r], t[r]);
+          });
+        }
+        dft_reg<R, S>(z);
+        if constexpr (LAST) {
+          sfor<0, R>([&](auto ri) {
+            v[vv * ES + q + decltype(ri)::value * Qb] = z[decltype(ri)::value];
+          });
+        } else {
+          const int j = l + q * T;
+          const int k = j & (NSp - 1);
+          const int base = (j - k) * R + k;
+          sfor<0, R>([&](auto ri) {
+            constexpr int r = decltype(ri)::value;
+            reg[vv * LB1 + lpad<PS>(base + r * NSp)] = z[r];
+          });
+        }
+      });
+    });
+    if constexpr (!LAST) wave_sync();
+  });
+}
+
+template <int N1, int ES, int V, int S, int PS, int NT, typename Real>
+__device__ __forceinline__ void stream_sub(cx<Real> (&v)[V * ES], cx<Real> *reg,
+                                           const cx<Real> (&tw)[NT], int l) {
+  if constexpr (NT == FftPlan<N1, ES>::P && NT != FftPlan<N1, ES>::NTW)
+    stream_wave_multi<N1, ES, V, S, PS>(v, reg, tw, l);
+  else
+    fft_wave_multi<N1, ES, V, S, PS>(v, reg, tw, l);
+}
+
+template <int N, int E, int V, int S, int PS, bool PRE, bool PB, typename Real>
 __device__ __forceinline__ void stream_fwdpath(cx<Real> (&v)[E], cx<Real> *X,
-                                               const StreamTw<N, E, V, Real> &tw, int w, int l) {
+                                               const StreamTw<N, E, V, PB, Real> &tw, int w,
+                                               int l) {
   using WP = WavePlan<N, E, V, 0>;
   constexpr int LB1 = LdsLen<WP::N1, PS>::value;
   constexpr int WV = WP::WV, ES = WP::ES;
@@ -78,17 +164,17 @@ __device__ __forceinline__ void stream_fwdpath(cx<Real> (&v)[E], cx<Real> *X,
     constexpr int vv = m / ES, j = m % ES;
     v[m] = X[(w * V + vv) * LB1 + lpad<PS>(l + 64 * j)];
   });
-  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  stream_sub<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
 }
 
-template <int N, int E, int V, int S, int PS, typename Real>
+template <int N, int E, int V, int S, int PS, bool PB, typename Real>
 __device__ __forceinline__ void stream_backpath(cx<Real> (&v)[E], cx<Real> *X, cx<Real> *Y,
-                                                const StreamTw<N, E, V, Real> &tw, int w,
+                                                const StreamTw<N, E, V, PB, Real> &tw, int w,
                                                 int l) {
   using WP = WavePlan<N, E, V, 0>;
   constexpr int LB1 = LdsLen<WP::N1, PS>::value;
   constexpr int WV = WP::WV, ES = WP::ES;
-  fft_wave_multi<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
+  stream_sub<WP::N1, ES, V, S, PS>(v, X + w * V * LB1, tw.sub, l);
   if (Y == X) wave_sync();  // own regions: the transform's last reads come first
   sfor<0, V>([&](auto vi) {
     constexpr int vv = decltype(vi)::value;
@@ -140,7 +226,7 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo,
 
 // D: prefetch distance of the stage arithmetic (slots whose operands are in
 // flight while one slot is computed).
-template <typename Real, int N, int E, int V, int PS, int D>
+template <typename Real, int N, int E, int V, int PS, int D, bool PB>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4_stream(RunArgs a) {
   constexpr int TP = 0;
@@ -169,7 +255,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   static_assert(WP::Q == 1, "one cross-wave element per slot");
   const int i0 = lane + 64 * w;
 
-  StreamTw<N, E, V, Real> tw;
+  StreamTw<N, E, V, PB, Real> tw;
   load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> v[E];
@@ -196,13 +282,13 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
       const __amdgpu_buffer_rsrc_t rIn = s == 0 ? rA : rU;
       const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
       // with one buffer the forward path fences the previous back path's reads
-      stream_fwdpath<N, E, V, +1, PS, !SH::TWO>(v, X, tw, w, lane);
+      stream_fwdpath<N, E, V, +1, PS, !SH::TWO, PB>(v, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
         v[m] = {p * v[m].re, p * v[m].im};
       });
-      stream_backpath<N, E, V, -1, PS>(v, X, Y, tw, w, lane);
+      stream_backpath<N, E, V, -1, PS, PB>(v, X, Y, tw, w, lane);
       // Stage arithmetic, slot by slot, with the loads of slot m + D issued
       // before slot m is computed (a ring of D slots of operands), so that
       // the global-memory latency is paid about once per stage.  v[m] is
@@ -267,35 +353,42 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS, int D>
+template <typename Real, int N, int E, int V, int PS, int D, bool PB>
 hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
   if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D>), dim3(a.count), dim3(SH::THREADS), 0,
+  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB>), dim3(a.count), dim3(SH::THREADS), 0,
                      st, a);
   return hipGetLastError();
 }
 
 // kind 13; two complex values of class workspace per mode (the accumulated
 // derivative and the stage input); no reverse sweep (the adjoint uses another
-// variant of the size)
-// (the tuning field holds D)
-template <typename Real, int N, int E, int V, int PS, int D> constexpr Variant stream_variant() {
+// variant of the size).  The tuning field holds D, plus 16 with PB.
+template <typename Real, int N, int E, int V, int PS, int D, bool PB>
+constexpr Variant stream_variant() {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D, 13, SH::IPB,
-                 SH::THREADS, SH::LDS_BYTES, &launch_stream_fwd<Real, N, E, V, PS, D>, nullptr,
-                 2};
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D + 16 * PB, 13,
+                 SH::IPB, SH::THREADS, SH::LDS_BYTES,
+                 &launch_stream_fwd<Real, N, E, V, PS, D, PB>, nullptr, 2};
 }
 
-// The first of each precision is the default (measured, us per step for 128
-// instances: FP64 D = 2 71.8, D = 1 72.5, D = 4 78.6, D = 8 92.1 (larger
-// rings spill); FP32 D = 4 48.5, D = 8 48.7).
+// The first of each precision is the default.  Measured, us per step for 1,
+// 100 and 128 instances: FP64 PB D = 1 58.8 / 65.6 / 68.9 (no spills),
+// PB D = 2 59.1 / 65.5 / 69.2, all powers held D = 2 59.5 / 66.6 / 70.0
+// (148 bytes of spills per lane); deeper rings spill and run slower
+// (PB D = 4: 59.6 / 67.2 / 70.6).  FP32 D = 4 45.1 / 46.5 / 47.4,
+// PB D = 8 44.9 / 46.5 / 47.0.  About a third of the FP64 step is the
+// stage arithmetic's global-memory traffic (336 bytes per mode and step,
+// which one CU streams at about 57 bytes per clock); the transforms alone
+// take about 40 us.
 static const Variant kStreamVariants[] = {
-    stream_variant<double, 8192, 16, 2, 3, 2>(),
-    stream_variant<double, 8192, 16, 2, 3, 1>(),
-    stream_variant<float, 8192, 16, 2, 3, 4>(),
-    stream_variant<float, 8192, 16, 2, 3, 8>(),
+    stream_variant<double, 8192, 16, 2, 3, 1, true>(),
+    stream_variant<double, 8192, 16, 2, 3, 2, true>(),
+    stream_variant<double, 8192, 16, 2, 3, 2, false>(),
+    stream_variant<float, 8192, 16, 2, 3, 8, true>(),
+    stream_variant<float, 8192, 16, 2, 3, 4, false>(),
 };
 
 const Variant *variants_stream(int *count) {
