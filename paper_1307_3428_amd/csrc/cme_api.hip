@@ -743,7 +743,13 @@ int cme_init(cme_plan **plan, int32_t batch, const cme_instance *inst, const dou
     d.sigma1 = x.sigma1;
     d.tau_ramp = x.tau_ramp;
     d.n = nt;
-    d.reserved = 0;
+    {
+      const double *kx = hk.data() + x.mode_offset;
+      bool same = !pad;
+      for (int i = 1; same && i < x.n_modes; ++i) same = kx[i] == kx[0];
+      d.kappa_uniform = same ? 1 : 0;
+      d.kappa0 = kx[0];
+    }
     if (pad) {
       pk.resize((size_t)(ptotal + nt), 1.0);
       po.resize((size_t)(ptotal + nt), 0.0);

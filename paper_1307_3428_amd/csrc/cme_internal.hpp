@@ -15,9 +15,11 @@ struct DevInst {
   double sqrt_kext;    // sqrt(kappa_ext), for the pump gradient
   double sigma0, sigma1, tau_ramp;
   int32_t n;
-  int32_t reserved;
+  int32_t kappa_uniform;  // 1: kappa_mu is the same for every mode (kappa0), and the
+                          // kernels that stream kappa from global memory may skip it
   int64_t a_offset;    // first element in the caller's packed state (padded plans:
                        // the state has n/2 modes per instance, kappa/omega' n)
+  double kappa0;       // kappa_mu of mode 0 (every mode when kappa_uniform)
 };
 
 // Arguments of one persistent forward launch over one size class.

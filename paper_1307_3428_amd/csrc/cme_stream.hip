@@ -3,20 +3,27 @@
 //
 // For the largest LDS-resident transforms (N = 8192: 128 KiB of FP64 field,
 // one instance per CU) a thread owns 16 modes, and holding the state y, the
-// accumulated derivative and the stage input in registers beside the
-// transform and its twiddles does not fit the 256 registers a lane has at two
+// RK4 partial update and the stage input in registers beside the transform
+// and its twiddles does not fit the 256 registers a lane has at two
 // wavefronts per SIMD.  Here only the stage input u_s lives in registers
 // across the two transforms of a stage; y is read from and written back to
-// the caller's state in place, and the accumulated derivative sits in the
-// class workspace (one complex value per mode).  Every access is coalesced
-// (lanes own consecutive modes) and the per-instance vectors (256 KiB in
-// FP64) stay in L2 / MALL, so the traffic they add is on-chip.
+// the caller's state in place, and the partial update and a copy of the
+// stage input sit in the class workspace (two complex values per mode).
+// Every access is coalesced (lanes own consecutive modes) and the
+// per-instance vectors stay in L2 / MALL, so the traffic they add is on-chip.
 //
 // Per RK4 stage s (Sec. 2; stage times t, t+h/2, t+h/2, t+h): a = IDFT(u_s),
 // b = |a|^2 a, NK = DFT(b) (Eq. (4), the 1/N folded into g0/N), then
 //   k_s = (-kappa/2 + i(omega' - sigma(t_s))) u_s + i (g0/N) NK + [mu = 0] pump,
-//   acc = k_1 (s = 1), acc += 2 k_s (s = 2, 3), and the next stage input
-//   u_{s+1} = y + c_{s+1} h k_s, or at s = 4 the update y += h/6 (acc + k_4).
+// the partial update P = y + h/6 k_1 + h/3 k_2 (s = 2), P += h/3 k_3 (s = 3),
+// and the next stage input u_{s+1} = y + c_{s+1} h k_s, or at s = 4 the new
+// state y = P + h/6 k_4.  Stage 1 stores k_1 alone (in P's place): stage 2
+// forms u_2 = y + h/2 k_1 and y + h/6 k_1 from it and y, so no copy of u_2 is
+// written; stage 4 does not read y.  Per mode and step that is 256 bytes of
+// global traffic (plus 32 for kappa where it varies over the modes; where it
+// is the same for every mode of an instance it is not read).
+#include <type_traits>
+
 #include "cme_lean.hpp"
 #include "cme_wave.hpp"
 
@@ -247,7 +254,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   constexpr int CB = (int)sizeof(cx<Real>);
   const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A, N * CB);
   cx<Real> *work = reinterpret_cast<cx<Real> *>(a.work) + (int64_t)slot * 2 * N;
-  const __amdgpu_buffer_rsrc_t rACC = buf_rsrc(work, N * CB);
+  const __amdgpu_buffer_rsrc_t rP = buf_rsrc(work, N * CB);
   const __amdgpu_buffer_rsrc_t rU = buf_rsrc(work + N, N * CB);
   const __amdgpu_buffer_rsrc_t rK = buf_rsrc(a.kappa + d.offset, N * 8);
   const __amdgpu_buffer_rsrc_t rW = buf_rsrc(a.omega + d.offset, N * 8);
@@ -263,93 +270,102 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   const Real gn = (Real)d.g0n;
   const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
   const double h = a.h;
-  const Real h2 = (Real)(0.5 * h), h1 = (Real)h, h6 = (Real)(h / 6.0), two = (Real)2;
+  const Real h2 = (Real)(0.5 * h), h1 = (Real)h, h3 = (Real)(h / 3.0), h6 = (Real)(h / 6.0);
   cx<Real> *ckpt = reinterpret_cast<cx<Real> *>(a.ckpt);
   int32_t to_ckpt = a.ckpt_every;
   int64_t ckpt_slot = 0;
   bool bad = false;
 
-  // the first stage input: the state
-  sfor<0, E>([&](auto mi) {
-    constexpr int m = decltype(mi)::value;
-    v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
-  });
-  for (int64_t n = 0; n < a.n_steps; ++n) {
-    const double t0 = (double)(a.step0 + n) * h;
-    sfor<0, 4>([&](auto si) {
-      constexpr int s = decltype(si)::value;
-      // the stage input u_s is in v; a copy sits in the state (s = 0) or U
-      const __amdgpu_buffer_rsrc_t rIn = s == 0 ? rA : rU;
-      const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
-      // with one buffer the forward path fences the previous back path's reads
-      stream_fwdpath<N, E, V, +1, PS, !SH::TWO, PB>(v, X, tw, w, lane);
-      sfor<0, E>([&](auto mi) {
-        constexpr int m = decltype(mi)::value;
-        const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
-        v[m] = {p * v[m].re, p * v[m].im};
-      });
-      stream_backpath<N, E, V, -1, PS, PB>(v, X, Y, tw, w, lane);
-      // Stage arithmetic, slot by slot, with the loads of slot m + D issued
-      // before slot m is computed (a ring of D slots of operands), so that
-      // the global-memory latency is paid about once per stage.  v[m] is
-      // consumed (N K) and refilled with the next stage input.
-      struct Ops {
-        cx<Real> u, acc, y;
-        double kap, om;
-      };
-      Ops ring[D];
-      __builtin_amdgcn_sched_barrier(0);  // no operand load above the transforms
-      auto fetch = [&](auto mi) {
-        constexpr int m = decltype(mi)::value;
-        constexpr int off = CB * WP::N1 * m;  // slot m: mode i0 + N1 m
-        Ops &o = ring[m % D];
-        o.u = buf_load<cx<Real>>(rIn, CB * i0, off);
-        o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
-        o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
-        if constexpr (s > 0) {
-          o.acc = buf_load<cx<Real>>(rACC, CB * i0, off);
-          o.y = buf_load<cx<Real>>(rA, CB * i0, off);
-        }
-      };
-      sfor<0, (D < E ? D : E)>(fetch);
-      sfor<0, E>([&](auto mi) {
-        constexpr int m = decltype(mi)::value;
-        __builtin_amdgcn_sched_barrier(0);
-        const Ops o = ring[m % D];
-        if constexpr (m + D < E) fetch(ic<m + D>{});
-        constexpr int off = CB * WP::N1 * m;
-        const Real lr = (Real)(-0.5 * o.kap);
-        const Real det = (Real)(o.om - sig);
-        const cx<Real> u = o.u;
-        cx<Real> k = {lr * u.re - det * u.im - gn * v[m].im, lr * u.im + det * u.re + gn * v[m].re};
-        if constexpr (m == E / 2) {
-          if (pump_owner) k = cadd(k, pump);
-        }
-        if constexpr (s == 0) {
-          buf_store(k, rACC, CB * i0, off);
-          v[m] = {u.re + h2 * k.re, u.im + h2 * k.im};  // u_2, with y = u_1
-          buf_store(v[m], rU, CB * i0, off);
-        } else if constexpr (s < 3) {
-          buf_store(cx<Real>{o.acc.re + two * k.re, o.acc.im + two * k.im}, rACC, CB * i0, off);
-          const Real c = s == 1 ? h2 : h1;
-          v[m] = {o.y.re + c * k.re, o.y.im + c * k.im};
-          buf_store(v[m], rU, CB * i0, off);
-        } else {
-          const cx<Real> tot = {o.acc.re + k.re, o.acc.im + k.im};
-          v[m] = {o.y.re + h6 * tot.re, o.y.im + h6 * tot.im};
-          buf_store(v[m], rA, CB * i0, off);
-          if (ckpt != nullptr && to_ckpt == 1)
-            ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = v[m];
-          if (n + 1 == a.n_steps) bad |= !(isfinite(v[m].re) && isfinite(v[m].im));
-        }
-      });
-      __builtin_amdgcn_sched_barrier(0);
+  // KU: kappa the same for every mode of the instance (not read per stage)
+  auto run = [&](auto ku) {
+    constexpr bool KU = decltype(ku)::value;
+    const Real lr0 = (Real)(-0.5 * d.kappa0);
+    // the first stage input: the state
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
     });
-    if (ckpt != nullptr && --to_ckpt == 0) {
-      to_ckpt = a.ckpt_every;
-      ++ckpt_slot;
+    for (int64_t n = 0; n < a.n_steps; ++n) {
+      const double t0 = (double)(a.step0 + n) * h;
+      sfor<0, 4>([&](auto si) {
+        constexpr int s = decltype(si)::value;
+        // the stage input u_s is in v (the transform overwrites it; the stage
+        // arithmetic reads it back from the state, k_1 or U)
+          const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
+        // with one buffer the forward path fences the previous back path's reads
+        stream_fwdpath<N, E, V, +1, PS, !SH::TWO, PB>(v, X, tw, w, lane);
+        sfor<0, E>([&](auto mi) {
+          constexpr int m = decltype(mi)::value;
+          const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
+          v[m] = {p * v[m].re, p * v[m].im};
+        });
+        stream_backpath<N, E, V, -1, PS, PB>(v, X, Y, tw, w, lane);
+        // Stage arithmetic, slot by slot, with the loads of slot m + D issued
+        // before slot m is computed (a ring of D slots of operands), so that
+        // the global-memory latency is paid about once per stage.  v[m] is
+        // consumed (N K) and refilled with the next stage input.
+        struct Ops {
+          cx<Real> u, part, y;
+          double kap, om;
+        };
+        Ops ring[D];
+        __builtin_amdgcn_sched_barrier(0);  // no operand load above the transforms
+        auto fetch = [&](auto mi) {
+          constexpr int m = decltype(mi)::value;
+          constexpr int off = CB * WP::N1 * m;  // slot m: mode i0 + N1 m
+          Ops &o = ring[m % D];
+          // stage input: y itself (s = 0), formed from y and k_1 (s = 1), or U
+          if constexpr (s == 0) o.u = buf_load<cx<Real>>(rA, CB * i0, off);
+          if constexpr (s >= 2) o.u = buf_load<cx<Real>>(rU, CB * i0, off);
+          if constexpr (!KU) o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
+          o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
+          if constexpr (s > 0) o.part = buf_load<cx<Real>>(rP, CB * i0, off);
+          if constexpr (s == 1 || s == 2) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
+        };
+        sfor<0, (D < E ? D : E)>(fetch);
+        sfor<0, E>([&](auto mi) {
+          constexpr int m = decltype(mi)::value;
+          __builtin_amdgcn_sched_barrier(0);
+          const Ops o = ring[m % D];
+          if constexpr (m + D < E) fetch(ic<m + D>{});
+          constexpr int off = CB * WP::N1 * m;
+          const Real lr = KU ? lr0 : (Real)(-0.5 * o.kap);
+          const Real det = (Real)(o.om - sig);
+          // s = 1: the slot holds k_1 in place of the partial update
+          const cx<Real> u = s == 1 ? cx<Real>{o.y.re + h2 * o.part.re, o.y.im + h2 * o.part.im}
+                                    : o.u;
+          cx<Real> k = {lr * u.re - det * u.im - gn * v[m].im, lr * u.im + det * u.re + gn * v[m].re};
+          if constexpr (m == E / 2) {
+            if (pump_owner) k = cadd(k, pump);
+          }
+          if constexpr (s == 0) {  // y = u_1; k_1 kept, u_2 formed again at s = 1
+            buf_store(k, rP, CB * i0, off);
+            v[m] = {u.re + h2 * k.re, u.im + h2 * k.im};
+          } else if constexpr (s < 3) {
+            const cx<Real> part = s == 1 ? cx<Real>{o.y.re + h6 * o.part.re, o.y.im + h6 * o.part.im}
+                                         : o.part;
+            buf_store(cx<Real>{part.re + h3 * k.re, part.im + h3 * k.im}, rP, CB * i0, off);
+            const Real c = s == 1 ? h2 : h1;
+            v[m] = {o.y.re + c * k.re, o.y.im + c * k.im};
+            buf_store(v[m], rU, CB * i0, off);
+          } else {
+            v[m] = {o.part.re + h6 * k.re, o.part.im + h6 * k.im};
+            buf_store(v[m], rA, CB * i0, off);
+            if (ckpt != nullptr && to_ckpt == 1)
+              ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = v[m];
+            if (n + 1 == a.n_steps) bad |= !(isfinite(v[m].re) && isfinite(v[m].im));
+          }
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      });
+      if (ckpt != nullptr && --to_ckpt == 0) {
+        to_ckpt = a.ckpt_every;
+        ++ckpt_slot;
+      }
     }
-  }
+  };
+  if (d.kappa_uniform) run(std::true_type{});
+  else run(std::false_type{});
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
@@ -363,8 +379,8 @@ hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// kind 13; two complex values of class workspace per mode (the accumulated
-// derivative and the stage input); no reverse sweep (the adjoint uses another
+// kind 13; two complex values of class workspace per mode (the partial
+// update and the stage input); no reverse sweep (the adjoint uses another
 // variant of the size).  The tuning field holds D, plus 16 with PB.
 template <typename Real, int N, int E, int V, int PS, int D, bool PB>
 constexpr Variant stream_variant() {
@@ -375,18 +391,16 @@ constexpr Variant stream_variant() {
 }
 
 // The first of each precision is the default.  Measured, us per step for 1,
-// 100 and 128 instances: FP64 PB D = 1 58.8 / 65.6 / 68.9 (no spills),
-// PB D = 2 59.1 / 65.5 / 69.2, all powers held D = 2 59.5 / 66.6 / 70.0
-// (148 bytes of spills per lane); deeper rings spill and run slower
-// (PB D = 4: 59.6 / 67.2 / 70.6).  FP32 D = 4 45.1 / 46.5 / 47.4,
-// PB D = 8 44.9 / 46.5 / 47.0.  About a third of the FP64 step is the
-// stage arithmetic's global-memory traffic (336 bytes per mode and step,
-// which one CU streams at about 57 bytes per clock); the transforms alone
-// take about 40 us.
+// 100 and 128 instances with per-mode kappa (kappa the same for every mode):
+// FP64 PB D = 2 55.7 / 61.2 / 64.0 (52.8 / 57.6 / 60.7), PB D = 1 56.4 /
+// 61.7 / 64.5 (52.8 / 58.2 / 60.9); with every twiddle power held the kernel
+// spills at any D.  FP32 PB D = 8 42.3 / 43.4 / 44.2 (38.9 / 39.7 / 40.5),
+// D = 4 42.4 / 43.8 / 44.2.  About a third of the FP64 step is the stage
+// arithmetic's global-memory traffic, which one CU streams at about 57 bytes
+// per clock; the transforms alone take about 40 us.
 static const Variant kStreamVariants[] = {
-    stream_variant<double, 8192, 16, 2, 3, 1, true>(),
     stream_variant<double, 8192, 16, 2, 3, 2, true>(),
-    stream_variant<double, 8192, 16, 2, 3, 2, false>(),
+    stream_variant<double, 8192, 16, 2, 3, 1, true>(),
     stream_variant<float, 8192, 16, 2, 3, 8, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, false>(),
 };

@@ -391,7 +391,7 @@ def random_batch(seed: int, sizes: Sequence[int], *, noise: float = 1e-3,
     for n in sizes:
         half = max(1, n // 2)
         kap0 = float(rng.uniform(0.8, 1.2))
-        kappa = kap0 * (1.0 + (0.2 * rng.uniform(-1, 1, n) if random_kappa else 0.0))
+        kappa = kap0 * (1.0 + (0.2 * rng.uniform(-1, 1, n) if random_kappa else np.zeros(n)))
         kappa[n // 2] = kap0
         d2 = float(rng.uniform(0.05, 0.9)) * max_detuning * 2.0 / half ** 2
         d3 = float(rng.uniform(-1.0, 1.0)) * 0.1 * max_detuning * 6.0 / half ** 3

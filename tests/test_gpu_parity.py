@@ -90,6 +90,42 @@ def test_each_kernel_variant_matches_oracle(cme, orc, n, kid):
     assert not st.any()
 
 
+def _stream_params():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(prec, k) for prec in (C.CME_F64, C.CME_F32) for k in C.cme_list_kernels(prec, 8192)
+                if C.cme_kernel_info(k)["kind"] == 13]
+    except Exception:
+        return [(0, 0)]
+
+
+@pytest.mark.parametrize("prec,kid", _stream_params())
+def test_stream_kernel_uniform_and_mixed_kappa(cme, orc, prec, kid):
+    """rk4_stream skips the kappa loads of instances whose kappa is the same for
+    every mode: one such instance beside one with per-mode kappa in the same
+    launch, against the oracle."""
+    info = cme.cme_kernel_info(kid)
+    print(f"variant {info['name']}", flush=True)
+    insts = (W.random_batch(4101, [8192], noise=1.0, random_kappa=False)
+             + W.random_batch(4102, [8192], noise=1.0))
+    for inst in insts:
+        inst.a0 = inst.a0 / math.sqrt(inst.n_modes)
+        inst.a0[inst.n_modes // 2] += 0.5
+    assert np.all(insts[0].kappa == insts[0].kappa[0]) and not np.all(insts[1].kappa == insts[1].kappa[0])
+    p = W.pack(insts)
+    steps, h = 6, 0.01
+    if prec == cme.CME_F64:
+        y, st = gpu_run(cme, p, h, steps, step0=3, kid=kid, n=8192)
+        tol = 1e-13
+    else:
+        y, st = gpu_run32(cme, p, h, steps, step0=3, kid=kid, n=8192)
+        tol = 2e-6
+    ref, _ = orc.run(p, h, steps, step0=3)
+    errs = per_instance_err(p, y, ref)
+    assert max(errs) <= tol, errs
+    assert not st.any()
+
+
 def test_mixed_sizes_in_one_plan(cme, orc):
     sizes = [16, 2048, 64, 128, 16, 1024, 256, 512, 32, 4096]
     insts = moderate_batch(77, sizes)
