@@ -166,10 +166,11 @@ def main() -> int:
     ap.add_argument("--staged-case", type=int, default=0, metavar="N",
                     help="only run the staged kernel on the staged leg's batch of size N "
                          "(8192, 16384 or 65536) for --rk-steps steps (profiling) and exit")
-    ap.add_argument("--profile-case", default="", metavar="N,B,KIND,PREC",
+    ap.add_argument("--profile-case", default="", metavar="N,B,KIND,PREC[,uniform]",
                     help="only run B seeded random instances of N modes on the first kernel "
                          "variant of that kind and precision (0 FP64, 1 FP32) for --rk-steps "
-                         "steps (profiling) and exit")
+                         "steps (profiling) and exit; 'uniform': kappa the same for every mode "
+                         "(as in the paper's normalised workloads) instead of per-mode kappa")
     ap.add_argument("--uneven-only", action="store_true",
                     help="only run the uneven-octave leg (profiling) and exit")
     ap.add_argument("--single-only", action="store_true",
@@ -214,9 +215,11 @@ def main() -> int:
         return 0
 
     if args.profile_case:
-        n, b, kind, prec = (int(x) for x in args.profile_case.split(","))
+        fields = args.profile_case.split(",")
+        n, b, kind, prec = (int(x) for x in fields[:4])
+        uniform = len(fields) > 4 and fields[4] == "uniform"
         kid = next(k for k in C.cme_list_kernels(prec, n) if C.cme_kernel_info(k)["kind"] == kind)
-        p = W.pack(W.random_batch(43, [n] * b, noise=1e-3))
+        p = W.pack(W.random_batch(43, [n] * b, noise=1e-3, random_kappa=not uniform))
         steps = args.rk_steps or 200
         with C.Plan(p, 2e-4, precision=prec) as plan:
             plan.select(n, kid)

@@ -7,19 +7,20 @@
 // and its twiddles does not fit the 256 registers a lane has at two
 // wavefronts per SIMD.  Here only the stage input u_s lives in registers
 // across the two transforms of a stage; y is read from and written back to
-// the caller's state in place, and the partial update and a copy of the
-// stage input sit in the class workspace (two complex values per mode).
+// the caller's state in place, and the stage derivatives, the partial update
+// and u_4 sit in the class workspace (two complex values per mode).
 // Every access is coalesced (lanes own consecutive modes) and the
 // per-instance vectors stay in L2 / MALL, so the traffic they add is on-chip.
 //
 // Per RK4 stage s (Sec. 2; stage times t, t+h/2, t+h/2, t+h): a = IDFT(u_s),
 // b = |a|^2 a, NK = DFT(b) (Eq. (4), the 1/N folded into g0/N), then
 //   k_s = (-kappa/2 + i(omega' - sigma(t_s))) u_s + i (g0/N) NK + [mu = 0] pump,
-// the partial update P = y + h/6 k_1 + h/3 k_2 (s = 2), P += h/3 k_3 (s = 3),
-// and the next stage input u_{s+1} = y + c_{s+1} h k_s, or at s = 4 the new
-// state y = P + h/6 k_4.  Stage 1 stores k_1 alone (in P's place): stage 2
-// forms u_2 = y + h/2 k_1 and y + h/6 k_1 from it and y, so no copy of u_2 is
-// written; stage 4 does not read y.  Per mode and step that is 256 bytes of
+// and the next stage input u_{s+1} = y + c_{s+1} h k_s.  Two workspace
+// vectors carry the step: stages 1 and 2 store k_1 and k_2 alone (the stage
+// inputs u_2 = y + h/2 k_1 and u_3 = y + h/2 k_2 are formed again from them
+// and y where needed), stage 3 stores the partial update
+// P = y + h/6 k_1 + h/3 k_2 + h/3 k_3 and u_4, and stage 4 writes the new state
+// y = P + h/6 k_4 without reading y.  Per mode and step that is 240 bytes of
 // global traffic (plus 32 for kappa where it varies over the modes; where it
 // is the same for every mode of an instance it is not read).
 #include <type_traits>
@@ -254,8 +255,8 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   constexpr int CB = (int)sizeof(cx<Real>);
   const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A, N * CB);
   cx<Real> *work = reinterpret_cast<cx<Real> *>(a.work) + (int64_t)slot * 2 * N;
-  const __amdgpu_buffer_rsrc_t rP = buf_rsrc(work, N * CB);
-  const __amdgpu_buffer_rsrc_t rU = buf_rsrc(work + N, N * CB);
+  const __amdgpu_buffer_rsrc_t rW1 = buf_rsrc(work, N * CB);
+  const __amdgpu_buffer_rsrc_t rW2 = buf_rsrc(work + N, N * CB);
   const __amdgpu_buffer_rsrc_t rK = buf_rsrc(a.kappa + d.offset, N * 8);
   const __amdgpu_buffer_rsrc_t rW = buf_rsrc(a.omega + d.offset, N * 8);
   // slot m of this thread holds mode i0 + N1 m (Q = 1)
@@ -305,7 +306,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
         // the global-memory latency is paid about once per stage.  v[m] is
         // consumed (N K) and refilled with the next stage input.
         struct Ops {
-          cx<Real> u, part, y;
+          cx<Real> y, w1, w2;
           double kap, om;
         };
         Ops ring[D];
@@ -314,13 +315,13 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           constexpr int m = decltype(mi)::value;
           constexpr int off = CB * WP::N1 * m;  // slot m: mode i0 + N1 m
           Ops &o = ring[m % D];
-          // stage input: y itself (s = 0), formed from y and k_1 (s = 1), or U
-          if constexpr (s == 0) o.u = buf_load<cx<Real>>(rA, CB * i0, off);
-          if constexpr (s >= 2) o.u = buf_load<cx<Real>>(rU, CB * i0, off);
+          // slot contents: W1 = k_1 (after s = 0) or P (after s = 2), W2 = k_2
+          // (after s = 1) or u_4 (after s = 2); y is the caller's state
+          if constexpr (s < 3) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
           if constexpr (!KU) o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
           o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
-          if constexpr (s > 0) o.part = buf_load<cx<Real>>(rP, CB * i0, off);
-          if constexpr (s == 1 || s == 2) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
+          if constexpr (s > 0) o.w1 = buf_load<cx<Real>>(rW1, CB * i0, off);
+          if constexpr (s > 1) o.w2 = buf_load<cx<Real>>(rW2, CB * i0, off);
         };
         sfor<0, (D < E ? D : E)>(fetch);
         sfor<0, E>([&](auto mi) {
@@ -331,25 +332,29 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           constexpr int off = CB * WP::N1 * m;
           const Real lr = KU ? lr0 : (Real)(-0.5 * o.kap);
           const Real det = (Real)(o.om - sig);
-          // s = 1: the slot holds k_1 in place of the partial update
-          const cx<Real> u = s == 1 ? cx<Real>{o.y.re + h2 * o.part.re, o.y.im + h2 * o.part.im}
-                                    : o.u;
+          // the stage input: y, y + h/2 k_1, y + h/2 k_2, u_4
+          cx<Real> u = o.y;
+          if constexpr (s == 1) u = {o.y.re + h2 * o.w1.re, o.y.im + h2 * o.w1.im};
+          if constexpr (s == 2) u = {o.y.re + h2 * o.w2.re, o.y.im + h2 * o.w2.im};
+          if constexpr (s == 3) u = o.w2;
           cx<Real> k = {lr * u.re - det * u.im - gn * v[m].im, lr * u.im + det * u.re + gn * v[m].re};
           if constexpr (m == E / 2) {
             if (pump_owner) k = cadd(k, pump);
           }
-          if constexpr (s == 0) {  // y = u_1; k_1 kept, u_2 formed again at s = 1
-            buf_store(k, rP, CB * i0, off);
+          if constexpr (s == 0) {  // W1 = k_1
+            buf_store(k, rW1, CB * i0, off);
             v[m] = {u.re + h2 * k.re, u.im + h2 * k.im};
-          } else if constexpr (s < 3) {
-            const cx<Real> part = s == 1 ? cx<Real>{o.y.re + h6 * o.part.re, o.y.im + h6 * o.part.im}
-                                         : o.part;
-            buf_store(cx<Real>{part.re + h3 * k.re, part.im + h3 * k.im}, rP, CB * i0, off);
-            const Real c = s == 1 ? h2 : h1;
-            v[m] = {o.y.re + c * k.re, o.y.im + c * k.im};
-            buf_store(v[m], rU, CB * i0, off);
+          } else if constexpr (s == 1) {  // W2 = k_2
+            buf_store(k, rW2, CB * i0, off);
+            v[m] = {o.y.re + h2 * k.re, o.y.im + h2 * k.im};
+          } else if constexpr (s == 2) {  // W1 = P = y + h/6 k_1 + h/3 k_2 + h/3 k_3, W2 = u_4
+            const cx<Real> p1 = {o.y.re + h6 * o.w1.re, o.y.im + h6 * o.w1.im};
+            const cx<Real> p2 = {p1.re + h3 * o.w2.re, p1.im + h3 * o.w2.im};
+            buf_store(cx<Real>{p2.re + h3 * k.re, p2.im + h3 * k.im}, rW1, CB * i0, off);
+            v[m] = {o.y.re + h1 * k.re, o.y.im + h1 * k.im};
+            buf_store(v[m], rW2, CB * i0, off);
           } else {
-            v[m] = {o.part.re + h6 * k.re, o.part.im + h6 * k.im};
+            v[m] = {o.w1.re + h6 * k.re, o.w1.im + h6 * k.im};
             buf_store(v[m], rA, CB * i0, off);
             if (ckpt != nullptr && to_ckpt == 1)
               ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = v[m];
@@ -379,8 +384,8 @@ hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// kind 13; two complex values of class workspace per mode (the partial
-// update and the stage input); no reverse sweep (the adjoint uses another
+// kind 13; two complex values of class workspace per mode (k_1, then the
+// partial update; k_2, then u_4); no reverse sweep (the adjoint uses another
 // variant of the size).  The tuning field holds D, plus 16 with PB.
 template <typename Real, int N, int E, int V, int PS, int D, bool PB>
 constexpr Variant stream_variant() {
@@ -392,10 +397,10 @@ constexpr Variant stream_variant() {
 
 // The first of each precision is the default.  Measured, us per step for 1,
 // 100 and 128 instances with per-mode kappa (kappa the same for every mode):
-// FP64 PB D = 2 55.7 / 61.2 / 64.0 (52.8 / 57.6 / 60.7), PB D = 1 56.4 /
-// 61.7 / 64.5 (52.8 / 58.2 / 60.9); with every twiddle power held the kernel
-// spills at any D.  FP32 PB D = 8 42.3 / 43.4 / 44.2 (38.9 / 39.7 / 40.5),
-// D = 4 42.4 / 43.8 / 44.2.  About a third of the FP64 step is the stage
+// FP64 PB D = 2 55.0 / 59.8 / 62.4 (51.6 / 56.4 / 59.1), PB D = 1 54.7 /
+// 60.4 / 63.3 (51.9 / 56.5 / 58.8); with every twiddle power held the kernel
+// spills at any D.  FP32 PB D = 8 41.5 / 42.7 / 44.0 (37.9 / 39.1 / 39.8),
+// D = 4 41.6 / 43.0 / 43.9.  About a quarter of the FP64 step is the stage
 // arithmetic's global-memory traffic, which one CU streams at about 57 bytes
 // per clock; the transforms alone take about 40 us.
 static const Variant kStreamVariants[] = {
