@@ -60,6 +60,7 @@ EPS = {FP64_TOL: 2.0 ** -53, FP32_TOL: 2.0 ** -24}   # unit roundoff of the prec
 
 
 SPREAD = 10.0   # sensitive horizons: within an order of magnitude of the twin's separation
+DELTA0 = 1e-12  # the twins' relative change of A(0)
 
 
 def check(label, y, ref, sep_whole, steps, tol=FP64_TOL, sep_side=None, after_sensitive=False):
@@ -74,14 +75,18 @@ def check(label, y, ref, sep_whole, steps, tol=FP64_TOL, sep_side=None, after_se
     horizon of the same run: what a sensitive stretch amplified stays in the
     state after it): the whole spectrum and the sidebands within SPREAD times
     the oracle's own spread under a 1e-12 change of A(0) (or the bars above,
-    if larger)."""
+    if larger).  A precision perturbs the state by about its unit roundoff
+    eps, not by 1e-12, so the separations are scaled by max(1, eps / 1e-12)
+    first: 1 in FP64, 6e4 in FP32, where a horizon is also sensitive once the
+    scaled separation exceeds the FP32 bar."""
     e = errors(y, ref)
-    sensitive = sep_whole > INSENSITIVE or after_sensitive
+    scale = max(1.0, EPS[tol] / DELTA0)
+    sensitive = sep_whole > INSENSITIVE or sep_whole * scale > tol or after_sensitive
     floor = EPS[tol] * np.sqrt(max(steps, 1)) / max(e["side_frac"], 1e-300)
-    whole_bar = max(tol, SPREAD * sep_whole) if sensitive else tol
+    whole_bar = max(tol, SPREAD * scale * sep_whole) if sensitive else tol
     side_bar = max(tol, floor)
     if sensitive and sep_side is not None:
-        side_bar = max(side_bar, SPREAD * sep_side)
+        side_bar = max(side_bar, SPREAD * scale * sep_side)
     print(f"{label}: whole {e['whole']:.2e} (bar {whole_bar:.1e}) side {e['side']:.2e} "
           f"(bar {side_bar:.1e}) power {e['power']:.2e} (sidebands hold {e['side_frac']:.1e} "
           f"of ||A||; twin separation {sep_whole:.1e}{', sensitive' if sensitive else ''})",
