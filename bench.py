@@ -11,8 +11,8 @@ steps / wall time, valid only where the GPU matches the FP64 oracle to
 bench times: after the full 5e4 steps against the oracle states stored in
 tests/golden/ (five instances: both detuning ends, two inside the
 modulation-instability window, the middle; with the oracle's own spread
-under a 1e-12 change of A(0)), and after 250 steps against the oracle run
-live on 16 instances, whose timing is the CPU baseline.  Errors are given
+under a 1e-12 change of A(0)), and after 640 steps against the oracle run
+live on 16 instances, whose timing (about 10 s) is the CPU baseline.  Errors are given
 for the whole spectrum and for the sidebands mu != 0 alone.
 
 Also reported on the same JSON line:
@@ -153,7 +153,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1, help="untimed full runs")
     ap.add_argument("--rk-steps", type=int, default=None,
                     help="RK4 steps per run (default: the workload's 5e4)")
-    ap.add_argument("--parity-steps", type=int, default=250,
+    ap.add_argument("--parity-steps", type=int, default=640,
                     help="RK4 steps of the live oracle sample (also the CPU baseline)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip adjoint / single-instance legs")
