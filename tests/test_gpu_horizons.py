@@ -39,8 +39,8 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def load(case):
     path = os.path.join(GOLDEN, f"oracle_{case}.npz")
-    if not os.path.exists(path):
-        pytest.skip(f"{path} not generated yet: python tests/golden/make_oracle_goldens.py {case}")
+    assert os.path.exists(path), (f"{path} is missing; it is written by "
+                                  f"python tests/golden/make_oracle_goldens.py {case}")
     d = np.load(path, allow_pickle=False)
     out = {k: d[k] for k in d.files if k != "meta"}
     out["meta"] = json.loads(str(d["meta"]))
