@@ -182,14 +182,16 @@ const Variant *default_variant(int precision, int n, int integrator) {
 }
 
 // Classic RK4 (cyclic sum) at N = 8192, by measured crossover (us per step
-// for the whole class):
+// for the whole class, per-mode kappa; kappa the same for every mode in
+// brackets):
 //   FP64: the staged kernels spread each instance over many CUs and win
-//   for small classes (four-wave workgroups: 39.7 at 1 instance, 70.5 at
-//   64); rk4_stream, one instance per CU with the state in global memory,
-//   above (58.8 at 1, 65.6 at 100, 68.9 at 128; staged 96.8, 111.5);
-//   FP32: the one-transform wave kernel for small classes (38.1 at 1, 40.1
-//   at 64), rk4_stream above (44.9 at 1, 46.5 at 100, 47.0 at 128; wave
-//   61.0, 66.6).
+//   for small classes (four-wave workgroups: 39.7 at 1 instance, 50.8 at
+//   24, 54.7 at 32, 61.6 at 40, 69.5 at 64); rk4_stream, one instance per
+//   CU with the state in global memory, from 32 on (55.4 (52.1) at 1,
+//   55.8 (52.5) at 24, 56.0 (52.4) at 32, 55.7 (52.3) at 40, 58.4 (55.6)
+//   at 64);
+//   FP32: rk4_stream at every size (38.5 (34.9) at 1 to 38.6 (35.2) at 64,
+//   against 38.3 ... 38.8 for the one-transform wave kernel, which spills).
 const Variant *class_default(int precision, int n, int integrator, size_t count) {
   const Variant *v = default_variant(precision, n, integrator);
   if (n != 8192 || integrator != CME_RK4) return v;
@@ -203,8 +205,8 @@ const Variant *class_default(int precision, int n, int integrator, size_t count)
     return nullptr;
   };
   const Variant *pick = nullptr;
-  if (precision == CME_F64) pick = count <= 48 ? find(6, 256) : find(13, 0);
-  else if (count > 80) pick = find(13, 0);
+  if (precision == CME_F64) pick = count < 32 ? find(6, 256) : find(13, 0);
+  else pick = find(13, 0);
   return pick ? pick : v;
 }
 

@@ -234,7 +234,10 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo,
 
 // D: prefetch distance of the stage arithmetic (slots whose operands are in
 // flight while one slot is computed).
-template <typename Real, int N, int E, int V, int PS, int D, bool PB>
+// YR: the state y held in registers for the whole launch (FP32, whose
+// registers have the room) instead of read from the caller's array at every
+// stage; it is written back after the last step.
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4_stream(RunArgs a) {
   constexpr int TP = 0;
@@ -267,6 +270,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> v[E];
+  cx<Real> yr[YR ? E : 1];
   const bool pump_owner = (w == 0 && lane == 0);  // mode N/2 sits in slot E/2 there
   const Real gn = (Real)d.g0n;
   const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
@@ -285,6 +289,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
+      if constexpr (YR) yr[m] = v[m];
     });
     for (int64_t n = 0; n < a.n_steps; ++n) {
       const double t0 = (double)(a.step0 + n) * h;
@@ -317,7 +322,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           Ops &o = ring[m % D];
           // slot contents: W1 = k_1 (after s = 0) or P (after s = 2), W2 = k_2
           // (after s = 1) or u_4 (after s = 2); y is the caller's state
-          if constexpr (s < 3) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
+          if constexpr (s < 3 && !YR) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
           if constexpr (!KU) o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
           o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
           if constexpr (s > 0) o.w1 = buf_load<cx<Real>>(rW1, CB * i0, off);
@@ -327,7 +332,8 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
         sfor<0, E>([&](auto mi) {
           constexpr int m = decltype(mi)::value;
           __builtin_amdgcn_sched_barrier(0);
-          const Ops o = ring[m % D];
+          Ops o = ring[m % D];
+          if constexpr (YR) o.y = yr[m];
           if constexpr (m + D < E) fetch(ic<m + D>{});
           constexpr int off = CB * WP::N1 * m;
           const Real lr = KU ? lr0 : (Real)(-0.5 * o.kap);
@@ -355,7 +361,12 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
             buf_store(v[m], rW2, CB * i0, off);
           } else {
             v[m] = {o.w1.re + h6 * k.re, o.w1.im + h6 * k.im};
-            buf_store(v[m], rA, CB * i0, off);
+            if constexpr (YR) {
+              yr[m] = v[m];
+              if (n + 1 == a.n_steps) buf_store(v[m], rA, CB * i0, off);
+            } else {
+              buf_store(v[m], rA, CB * i0, off);
+            }
             if (ckpt != nullptr && to_ckpt == 1)
               ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = v[m];
             if (n + 1 == a.n_steps) bad |= !(isfinite(v[m].re) && isfinite(v[m].im));
@@ -374,38 +385,42 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS, int D, bool PB>
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR>
 hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
   if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB>), dim3(a.count), dim3(SH::THREADS), 0,
+  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB, YR>), dim3(a.count), dim3(SH::THREADS), 0,
                      st, a);
   return hipGetLastError();
 }
 
 // kind 13; two complex values of class workspace per mode (k_1, then the
 // partial update; k_2, then u_4); no reverse sweep (the adjoint uses another
-// variant of the size).  The tuning field holds D, plus 16 with PB.
-template <typename Real, int N, int E, int V, int PS, int D, bool PB>
+// variant of the size).  The tuning field holds D, plus 16 with PB and 32 with YR.
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR = false>
 constexpr Variant stream_variant() {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D + 16 * PB, 13,
-                 SH::IPB, SH::THREADS, SH::LDS_BYTES,
-                 &launch_stream_fwd<Real, N, E, V, PS, D, PB>, nullptr, 2};
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D + 16 * PB + 32 * YR,
+                 13, SH::IPB, SH::THREADS, SH::LDS_BYTES,
+                 &launch_stream_fwd<Real, N, E, V, PS, D, PB, YR>, nullptr, 2};
 }
 
 // The first of each precision is the default.  Measured, us per step for 1,
 // 100 and 128 instances with per-mode kappa (kappa the same for every mode):
 // FP64 PB D = 2 55.0 / 59.8 / 62.4 (51.6 / 56.4 / 59.1), PB D = 1 54.7 /
 // 60.4 / 63.3 (51.9 / 56.5 / 58.8); with every twiddle power held the kernel
-// spills at any D.  FP32 PB D = 8 41.5 / 42.7 / 44.0 (37.9 / 39.1 / 39.8),
-// D = 4 41.6 / 43.0 / 43.9.  About a quarter of the FP64 step is the stage
-// arithmetic's global-memory traffic, which one CU streams at about 57 bytes
-// per clock; the transforms alone take about 40 us.
+// spills at any D, and the FP64 state does not fit beside the transform.
+// FP32 YR PB D = 4 38.1 / 39.5 / 40.1 (34.7 / 35.9 / 36.7), YR PB D = 8
+// 38.3 / 39.4 / 40.1 (34.8 / 35.9 / 36.8), PB D = 8 without YR 41.5 / 42.7 /
+// 44.0 (37.9 / 39.1 / 39.8), D = 4 41.6 / 43.0 / 43.9.  About a quarter of
+// the FP64 step is the stage arithmetic's global-memory traffic, which one CU
+// streams at about 57 bytes per clock; the transforms alone take about 40 us.
 static const Variant kStreamVariants[] = {
     stream_variant<double, 8192, 16, 2, 3, 2, true>(),
     stream_variant<double, 8192, 16, 2, 3, 1, true>(),
+    stream_variant<float, 8192, 16, 2, 3, 4, true, true>(),
+    stream_variant<float, 8192, 16, 2, 3, 8, true, true>(),
     stream_variant<float, 8192, 16, 2, 3, 8, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, false>(),
 };
