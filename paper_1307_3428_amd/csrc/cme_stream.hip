@@ -20,9 +20,10 @@
 // inputs u_2 = y + h/2 k_1 and u_3 = y + h/2 k_2 are formed again from them
 // and y where needed), stage 3 stores the partial update
 // P = y + h/6 k_1 + h/3 k_2 + h/3 k_3 and u_4, and stage 4 writes the new state
-// y = P + h/6 k_4 without reading y.  Per mode and step that is 240 bytes of
-// global traffic (plus 32 for kappa where it varies over the modes; where it
-// is the same for every mode of an instance it is not read).
+// y = P + h/6 k_4 without reading y.  Per mode and step that is 208 bytes of
+// global traffic in FP64 with omega' held in registers (plus 32 for kappa
+// where it varies over the modes; where it is the same for every mode of an
+// instance it is not read), and in FP32, with y in registers too, 72 bytes.
 #include <type_traits>
 
 #include "cme_lean.hpp"
@@ -236,8 +237,10 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo,
 // flight while one slot is computed).
 // YR: the state y held in registers for the whole launch (FP32, whose
 // registers have the room) instead of read from the caller's array at every
-// stage; it is written back after the last step.
-template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR>
+// stage; it is written back after the last step.  OR: omega' held in
+// registers for the launch (16 values per thread) instead of read at every
+// stage.
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4_stream(RunArgs a) {
   constexpr int TP = 0;
@@ -271,6 +274,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
 
   cx<Real> v[E];
   cx<Real> yr[YR ? E : 1];
+  double omr[OR ? E : 1];
   const bool pump_owner = (w == 0 && lane == 0);  // mode N/2 sits in slot E/2 there
   const Real gn = (Real)d.g0n;
   const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
@@ -290,6 +294,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
       constexpr int m = decltype(mi)::value;
       v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
       if constexpr (YR) yr[m] = v[m];
+      if constexpr (OR) omr[m] = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
     });
     for (int64_t n = 0; n < a.n_steps; ++n) {
       const double t0 = (double)(a.step0 + n) * h;
@@ -324,7 +329,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           // (after s = 1) or u_4 (after s = 2); y is the caller's state
           if constexpr (s < 3 && !YR) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
           if constexpr (!KU) o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
-          o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
+          if constexpr (!OR) o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
           if constexpr (s > 0) o.w1 = buf_load<cx<Real>>(rW1, CB * i0, off);
           if constexpr (s > 1) o.w2 = buf_load<cx<Real>>(rW2, CB * i0, off);
         };
@@ -334,6 +339,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           __builtin_amdgcn_sched_barrier(0);
           Ops o = ring[m % D];
           if constexpr (YR) o.y = yr[m];
+          if constexpr (OR) o.om = omr[m];
           if constexpr (m + D < E) fetch(ic<m + D>{});
           constexpr int off = CB * WP::N1 * m;
           const Real lr = KU ? lr0 : (Real)(-0.5 * o.kap);
@@ -385,43 +391,49 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR>
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR>
 hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
   if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB, YR>), dim3(a.count), dim3(SH::THREADS), 0,
+  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB, YR, OR>), dim3(a.count), dim3(SH::THREADS), 0,
                      st, a);
   return hipGetLastError();
 }
 
 // kind 13; two complex values of class workspace per mode (k_1, then the
 // partial update; k_2, then u_4); no reverse sweep (the adjoint uses another
-// variant of the size).  The tuning field holds D, plus 16 with PB and 32 with YR.
-template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR = false>
+// variant of the size).  The tuning field holds D, plus 16 with PB, 32 with YR
+// and 64 with OR.
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR = false,
+          bool OR = false>
 constexpr Variant stream_variant() {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D + 16 * PB + 32 * YR,
-                 13, SH::IPB, SH::THREADS, SH::LDS_BYTES,
-                 &launch_stream_fwd<Real, N, E, V, PS, D, PB, YR>, nullptr, 2};
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS,
+                 D + 16 * PB + 32 * YR + 64 * OR, 13, SH::IPB, SH::THREADS, SH::LDS_BYTES,
+                 &launch_stream_fwd<Real, N, E, V, PS, D, PB, YR, OR>, nullptr, 2};
 }
 
 // The first of each precision is the default.  Measured, us per step for 1,
 // 100 and 128 instances with per-mode kappa (kappa the same for every mode):
-// FP64 PB D = 2 55.0 / 59.8 / 62.4 (51.6 / 56.4 / 59.1), PB D = 1 54.7 /
-// 60.4 / 63.3 (51.9 / 56.5 / 58.8); with every twiddle power held the kernel
-// spills at any D, and the FP64 state does not fit beside the transform.
-// FP32 YR PB D = 4 38.1 / 39.5 / 40.1 (34.7 / 35.9 / 36.7), YR PB D = 8
-// 38.3 / 39.4 / 40.1 (34.8 / 35.9 / 36.8), PB D = 8 without YR 41.5 / 42.7 /
-// 44.0 (37.9 / 39.1 / 39.8), D = 4 41.6 / 43.0 / 43.9.  About a quarter of
-// the FP64 step is the stage arithmetic's global-memory traffic, which one CU
-// streams at about 57 bytes per clock; the transforms alone take about 40 us.
+// FP64 OR PB D = 1 52.1 / 56.7 / 57.8 (49.0 / 53.6 / 55.7; 255 VGPRs, no
+// spills), OR PB D = 2 52.1 / 56.3 / 57.1 (48.9 / 53.2 / 54.8; spills 36
+// bytes per lane), PB D = 2 55.3 / 59.7 / 61.2 (51.5 / 56.2 / 58.0), PB D = 1
+// 54.8 / 60.0 / 61.1 (52.0 / 56.1 / 58.3); with every twiddle power held the
+// kernel spills at any D, and the FP64 state does not fit beside the
+// transform.  FP32 YR OR PB D = 4 34.6 / 35.5 / 37.1 (31.0 / 32.2 / 32.7),
+// YR OR PB D = 2 34.8 / 35.9 / 37.5 (31.1 / 32.2 / 32.7), YR PB D = 4 38.2 /
+// 39.0 / 40.0 (34.6 / 35.5 / 36.7), D = 4 41.5 / 43.3 / 43.7 (38.1 / 39.1 /
+// 39.8).  The stage arithmetic's global-memory traffic is streamed by one CU
+// at about 57 bytes per clock; the transforms alone take about 40 us (FP64).
 static const Variant kStreamVariants[] = {
+    stream_variant<double, 8192, 16, 2, 3, 1, true, false, true>(),
+    stream_variant<double, 8192, 16, 2, 3, 2, true, false, true>(),
     stream_variant<double, 8192, 16, 2, 3, 2, true>(),
     stream_variant<double, 8192, 16, 2, 3, 1, true>(),
+    stream_variant<float, 8192, 16, 2, 3, 4, true, true, true>(),
+    stream_variant<float, 8192, 16, 2, 3, 2, true, true, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, true, true>(),
-    stream_variant<float, 8192, 16, 2, 3, 8, true, true>(),
-    stream_variant<float, 8192, 16, 2, 3, 8, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, false>(),
 };
 
