@@ -23,7 +23,8 @@
 // y = P + h/6 k_4 without reading y.  Per mode and step that is 208 bytes of
 // global traffic in FP64 with omega' held in registers (plus 32 for kappa
 // where it varies over the modes; where it is the same for every mode of an
-// instance it is not read), and in FP32, with y in registers too, 72 bytes.
+// instance it is not read), and in FP32, with y and -kappa/2 in registers
+// too, 72 bytes whatever kappa.
 #include <type_traits>
 
 #include "cme_lean.hpp"
@@ -239,7 +240,7 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo,
 // registers have the room) instead of read from the caller's array at every
 // stage; it is written back after the last step.  OR: omega' held in
 // registers for the launch (16 values per thread) instead of read at every
-// stage.
+// stage, and in FP32 -kappa/2 as well.
 template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4_stream(RunArgs a) {
@@ -275,6 +276,9 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   cx<Real> v[E];
   cx<Real> yr[YR ? E : 1];
   double omr[OR ? E : 1];
+  // FP32 with OR: -kappa/2 too, already rounded to the stage arithmetic's precision
+  constexpr bool LRR = OR && sizeof(Real) == 4;
+  Real lrr[LRR ? E : 1];
   const bool pump_owner = (w == 0 && lane == 0);  // mode N/2 sits in slot E/2 there
   const Real gn = (Real)d.g0n;
   const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
@@ -295,6 +299,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
       v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
       if constexpr (YR) yr[m] = v[m];
       if constexpr (OR) omr[m] = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
+      if constexpr (LRR) lrr[m] = (Real)(-0.5 * buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m));
     });
     for (int64_t n = 0; n < a.n_steps; ++n) {
       const double t0 = (double)(a.step0 + n) * h;
@@ -328,7 +333,7 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           // slot contents: W1 = k_1 (after s = 0) or P (after s = 2), W2 = k_2
           // (after s = 1) or u_4 (after s = 2); y is the caller's state
           if constexpr (s < 3 && !YR) o.y = buf_load<cx<Real>>(rA, CB * i0, off);
-          if constexpr (!KU) o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
+          if constexpr (!KU && !LRR) o.kap = buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m);
           if constexpr (!OR) o.om = buf_load<double>(rW, 8 * i0, 8 * WP::N1 * m);
           if constexpr (s > 0) o.w1 = buf_load<cx<Real>>(rW1, CB * i0, off);
           if constexpr (s > 1) o.w2 = buf_load<cx<Real>>(rW2, CB * i0, off);
@@ -342,7 +347,9 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
           if constexpr (OR) o.om = omr[m];
           if constexpr (m + D < E) fetch(ic<m + D>{});
           constexpr int off = CB * WP::N1 * m;
-          const Real lr = KU ? lr0 : (Real)(-0.5 * o.kap);
+          Real lr = lr0;
+          if constexpr (!KU && LRR) lr = lrr[m];
+          if constexpr (!KU && !LRR) lr = (Real)(-0.5 * o.kap);
           const Real det = (Real)(o.om - sig);
           // the stage input: y, y + h/2 k_1, y + h/2 k_2, u_4
           cx<Real> u = o.y;
@@ -421,10 +428,10 @@ constexpr Variant stream_variant() {
 // bytes per lane), PB D = 2 55.3 / 59.7 / 61.2 (51.5 / 56.2 / 58.0), PB D = 1
 // 54.8 / 60.0 / 61.1 (52.0 / 56.1 / 58.3); with every twiddle power held the
 // kernel spills at any D, and the FP64 state does not fit beside the
-// transform.  FP32 YR OR PB D = 4 34.6 / 35.5 / 37.1 (31.0 / 32.2 / 32.7),
-// YR OR PB D = 2 34.8 / 35.9 / 37.5 (31.1 / 32.2 / 32.7), YR PB D = 4 38.2 /
-// 39.0 / 40.0 (34.6 / 35.5 / 36.7), D = 4 41.5 / 43.3 / 43.7 (38.1 / 39.1 /
-// 39.8).  The stage arithmetic's global-memory traffic is streamed by one CU
+// transform.  FP32 YR OR PB D = 4 31.3 / 31.8 / 32.9 (31.1 / 32.2 / 32.3),
+// YR OR PB D = 2 31.4 / 32.1 / 32.4 (31.3 / 31.9 / 32.7), YR PB D = 4 38.5 /
+// 39.2 / 39.9 (34.7 / 35.5 / 36.3), D = 4 41.8 / 42.8 / 43.6 (38.2 / 39.2 /
+// 39.7).  The stage arithmetic's global-memory traffic is streamed by one CU
 // at about 57 bytes per clock; the transforms alone take about 40 us (FP64).
 static const Variant kStreamVariants[] = {
     stream_variant<double, 8192, 16, 2, 3, 1, true, false, true>(),
