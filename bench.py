@@ -598,11 +598,12 @@ def uneven_leg(C, W, torch, steps=20000):
     return out
 
 
-# HBM bytes per mode and RK4 step of the staged kernels: per stage the
-# column kernel reads S and y (+ u, acc after the first stage) and kappa,
-# omega' and writes S (+ u, acc; y at the last stage); the row kernel reads
-# and writes S.  16 B per complex value, 8 per real.
-STAGED_BYTES_PER_MODE_STEP = (16 * 5 + 16) + 2 * (16 * 7 + 16) + (16 * 6 + 16) + 4 * 32
+# HBM bytes per mode and RK4 step of the staged kernels (per-mode kappa, as in
+# the seeded batches of this leg): per stage the column kernel reads S, kappa,
+# omega' and stage 1: y; stage 2: y, k_1; stage 3: y, k_1, k_2; stage 4: P, u_4,
+# and writes S and stage 1: k_1; stage 2: k_2; stage 3: P, u_4; stage 4: y;
+# the row kernel reads and writes S.  16 B per complex value, 8 per real.
+STAGED_BYTES_PER_MODE_STEP = (16 * 4 + 16) + (16 * 5 + 16) + (16 * 7 + 16) + (16 * 5 + 16) + 4 * 32
 # split-step on the staged transforms: the row kernel reads and writes S, the
 # column kernel reads and writes S and reads kappa and omega'
 SPLIT_STAGED_BYTES_PER_MODE_STEP = 32 + 32 + 16

@@ -22,10 +22,12 @@
 //     (outer sum over m1), cube pointwise, start the forward transform (inner
 //     sum over j1, times w^{-j2 m1}) into S.
 // A step is 4 x (row, column) launches; a run starts with one column launch
-// that only starts the inverse transform of the state.  The RK4 vectors
-// (accumulated derivative, stage input) live in a plan-owned workspace next to
-// S; the state is read and written in the caller's array.  Every launch moves
-// each of these arrays once, so the path is bound by memory traffic.
+// that only starts the inverse transform of the state.  Two RK4 vectors live
+// in a plan-owned workspace next to S (classic RK4: k_1, then the partial
+// update; k_2, then u_4; the interaction picture: the accumulated derivative
+// and the stage input); the state is read and written in the caller's array.
+// Every launch moves each of these arrays at most once, so the path is bound
+// by memory traffic.
 //
 // Each team transforms its column or row with the radix-E Stockham passes of
 // cme_fft.hpp in registers, exchanging through a private LDS buffer inside
@@ -50,7 +52,7 @@ template <typename Real> struct StagedArgsT {
   const double *kappa;
   const double *omega;
   const cx<Real> *tab;     // exp(-2 pi i k / N), k < N
-  cx<Real> *work;          // per class slot: S, acc, u (3 N each)
+  cx<Real> *work;          // per class slot: S and the two RK4 vectors (3 N each)
   double h;
   double t0;               // time at the start of the step
   cx<Real> *ckpt;          // checkpoint row for this step (packed like A) or null
@@ -218,34 +220,53 @@ __global__ void __launch_bounds__(64 * WPB) staged_col(StagedArgsT<Real> a) {
         v[m] = nxt;
       });
     } else {
+    // Two workspace vectors carry the step (as in cme_stream.hip): W1 holds
+    // k_1 after stage 1 and P = y + h/6 k_1 + h/3 k_2 + h/3 k_3 after stage 3,
+    // W2 holds k_2 after stage 2 and u_4 after stage 3; u_2 and u_3 are formed
+    // again from y and k_1, k_2, and stage 4 does not read y.  kappa is not
+    // read where it is the same for every mode of the instance.
     const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, a.t0 + stage_c(STAGE) * h);
-    const Real cn = (Real)(STAGE == 0 || STAGE == 1 ? 0.5 * h : h), h6 = (Real)(h / 6.0);
-    const Real two = (Real)2;
+    const Real h2 = (Real)(0.5 * h), h1 = (Real)h, h3 = (Real)(h / 3.0), h6 = (Real)(h / 6.0);
+    const bool ku = d.kappa_uniform != 0;
+    const Real lr0 = (Real)(-0.5 * d.kappa0);
+    cx<Real> *W1 = ACC, *W2 = U;
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const int i = m1 + N1 * (t + m * T);
       const bool band = in_band(i);
-      const cx<Real> y = band ? A[phys(i)] : cx<Real>{(Real)0, (Real)0};
-      const cx<Real> u = STAGE == 0 ? y : U[i];
+      const cx<Real> zero = {(Real)0, (Real)0};
+      cx<Real> y = zero, w1 = zero, w2 = zero, u;
+      if constexpr (STAGE < 3) {
+        if (band) y = A[phys(i)];
+      }
+      if constexpr (STAGE == 1 || STAGE == 2) w1 = W1[i];
+      if constexpr (STAGE >= 2) w2 = W2[i];
+      if constexpr (STAGE == 0) u = y;
+      if constexpr (STAGE == 1) u = {y.re + h2 * w1.re, y.im + h2 * w1.im};
+      if constexpr (STAGE == 2) u = {y.re + h2 * w2.re, y.im + h2 * w2.im};
+      if constexpr (STAGE == 3) u = w2;
       const cx<Real> nk = v[m];
-      const Real lr = (Real)(-0.5 * kap[i]), li = (Real)(omg[i] - sig);
+      const Real lr = ku ? lr0 : (Real)(-0.5 * kap[i]), li = (Real)(omg[i] - sig);
       // k = L u + i (g0/N) N K
       cx<Real> k = {lr * u.re - li * u.im - gn * nk.im, lr * u.im + li * u.re + gn * nk.re};
       if (i == N / 2) k = cadd(k, pump);
-      if (!band) k = {(Real)0, (Real)0};
+      if (!band) k = zero;
       cx<Real> nxt;
       if constexpr (STAGE == 0) {
-        ACC[i] = k;
-        nxt = {y.re + cn * k.re, y.im + cn * k.im};
-        U[i] = nxt;
-      } else if constexpr (STAGE < 3) {
-        const cx<Real> acc = ACC[i];
-        ACC[i] = {acc.re + two * k.re, acc.im + two * k.im};
-        nxt = {y.re + cn * k.re, y.im + cn * k.im};
-        U[i] = nxt;
+        W1[i] = k;
+        nxt = {y.re + h2 * k.re, y.im + h2 * k.im};
+      } else if constexpr (STAGE == 1) {
+        W2[i] = k;
+        nxt = {y.re + h2 * k.re, y.im + h2 * k.im};
+      } else if constexpr (STAGE == 2) {
+        const cx<Real> p1 = {y.re + h6 * w1.re, y.im + h6 * w1.im};
+        const cx<Real> p2 = {p1.re + h3 * w2.re, p1.im + h3 * w2.im};
+        W1[i] = {p2.re + h3 * k.re, p2.im + h3 * k.im};
+        nxt = {y.re + h1 * k.re, y.im + h1 * k.im};
+        W2[i] = nxt;
       } else {
-        const cx<Real> acc = ACC[i];
-        nxt = {y.re + h6 * (acc.re + k.re), y.im + h6 * (acc.im + k.im)};
+        const cx<Real> p = W1[i];
+        nxt = {p.re + h6 * k.re, p.im + h6 * k.im};
         if (band) {
           A[phys(i)] = nxt;
           if (a.ckpt) a.ckpt[d.a_offset + phys(i)] = nxt;
