@@ -221,7 +221,8 @@ def main() -> int:
         kid = next(k for k in C.cme_list_kernels(prec, n) if C.cme_kernel_info(k)["kind"] == kind)
         p = W.pack(W.random_batch(43, [n] * b, noise=1e-3, random_kappa=not uniform))
         steps = args.rk_steps or 200
-        with C.Plan(p, 2e-4, precision=prec) as plan:
+        integ = C.CME_RK4IP if kind in (7, 8, 12, 14) else C.CME_RK4
+        with C.Plan(p, 2e-4, precision=prec, integrator=integ) as plan:
             plan.select(n, kid)
             A = plan.state(p.a0)
             s = timed_run(plan, A, steps, torch)

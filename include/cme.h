@@ -258,14 +258,17 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * picture RK4 on that transform, 13: RK4 on the two-level transform with
  * the state, the stage input and the accumulated derivative in global
  * memory (one instance per workgroup; the plan holds a workspace of 2 N
- * complex values per instance); the staged kinds 6, 8, 9, 10 carry the
+ * complex values per instance), 14: interaction-picture RK4 on that layout
+ * (a workspace of 3 N); the staged kinds 6, 8, 9, 10 carry the
  * row length N1 in the V field), instances per workgroup,
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
  * twiddles are held in registers; kinds 6, 8, 9, 10: wavefronts per
  * workgroup; kind 13: operand prefetch distance of the stage arithmetic, + 16
- * when the sub-transform twiddles are formed from one base per pass).
+ * when the sub-transform twiddles are formed from one base per pass, + 32 with
+ * the state and + 64 with omega' held in registers; kind 14: the prefetch
+ * distance).
  * Returns 10, or CME_EINVAL. */
 int cme_kernel_info(int32_t kernel_id, int32_t *info, int32_t cap);
 

@@ -227,7 +227,7 @@ def cme_kernel_info(kernel_id: int) -> dict:
     info["id"] = int(kernel_id)
     info["threads_per_instance"] = info["n_modes"] // info["elems_per_thread"]
     info["name"] = ({0: "rk4_persistent", 1: "rk4_wave", 2: "rk4_duo", 3: "rk4_lean", 4: "split_lean", 5: "rk4_wave_pad", 6: "rk4_staged", 7: "rk4ip_wave", 8: "rk4ip_staged", 9: "split_staged", 10: "rk4_staged_pad", 11: "rk4_lean_pad", 12: "rk4ip_lean",
-                     13: "rk4_stream"}[info["kind"]]
+                     13: "rk4_stream", 14: "rk4ip_stream"}[info["kind"]]
                     + "<{},{},{},{},{}{}>".format(
                         "double" if info["precision"] == 0 else "float", info["n_modes"],
                         info["elems_per_thread"], info["sub_transforms"], info["pad_shift"],

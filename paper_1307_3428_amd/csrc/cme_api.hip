@@ -166,7 +166,7 @@ bool integrates(const Variant &v, int integrator) {
   if (fwm == CME_FWM_PADDED) return v.kind == 5 || v.kind == 10 || v.kind == 11;
   if (v.kind == 5 || v.kind == 10 || v.kind == 11) return false;
   if (v.kind == 4 || v.kind == 9) return integ == CME_SPLIT_STEP;
-  if (v.kind == 7 || v.kind == 8 || v.kind == 12) return integ == CME_RK4IP;
+  if (v.kind == 7 || v.kind == 8 || v.kind == 12 || v.kind == 14) return integ == CME_RK4IP;
   return integ == CME_RK4;
 }
 
@@ -192,9 +192,17 @@ const Variant *default_variant(int precision, int n, int integrator) {
 //   at 64);
 //   FP32: rk4_stream at every size (38.5 (34.9) at 1 to 38.6 (35.2) at 64,
 //   against 38.3 ... 38.8 for the one-transform wave kernel, which spills).
+// RK4IP at N = 8192:
+//   FP64: rk4ip_stream at every size (49.9 at 1, 53.2 at 64, 56.6 at 128
+//   instances, against 58.5, 78.9 and 96.8 for the staged kernels and 96 to
+//   126 for the one-transform wave kernel);
+//   FP32: the wave kernel, its state in registers, for small classes (30.8
+//   at 16, 31.2 at 64, 35.0 at 100, 36.3 at 112), rk4ip_stream from 112 on
+//   (35.9 at 16, 36.5 at 100, 36.5 at 112, 36.4 at 128, against 39.6 for
+//   the wave kernel, whose spill traffic grows with the class).
 const Variant *class_default(int precision, int n, int integrator, size_t count) {
   const Variant *v = default_variant(precision, n, integrator);
-  if (n != 8192 || integrator != CME_RK4) return v;
+  if (n != 8192 || (integrator != CME_RK4 && integrator != CME_RK4IP)) return v;
   int cnt = 0;
   const Variant *all = all_variants(&cnt);
   auto find = [&](int kind, int threads) -> const Variant * {
@@ -205,7 +213,9 @@ const Variant *class_default(int precision, int n, int integrator, size_t count)
     return nullptr;
   };
   const Variant *pick = nullptr;
-  if (precision == CME_F64) pick = count < 32 ? find(6, 256) : find(13, 0);
+  if (integrator == CME_RK4IP)
+    pick = precision == CME_F32 && count < 112 ? find(7, 0) : find(14, 0);
+  else if (precision == CME_F64) pick = count < 32 ? find(6, 256) : find(13, 0);
   else pick = find(13, 0);
   return pick ? pick : v;
 }

@@ -118,7 +118,8 @@ struct Variant {
                    // padded sum on the lean kernel (cme_lean.hip), 12: interaction-
                    // picture RK4 on the lean kernel (cme_lean.hip), 13: RK4 on the
                    // two-level transform with the RK4 vectors in global memory
-                   // (cme_stream.hip)
+                   // (cme_stream.hip), 14: interaction-picture RK4 on that
+                   // layout (cme_stream.hip)
   int ipb;         // instances per workgroup
   int threads;     // workgroup size
   int lds_bytes;   // static LDS per workgroup

@@ -421,6 +421,165 @@ constexpr Variant stream_variant() {
                  &launch_stream_fwd<Real, N, E, V, PS, D, PB, YR, OR>, nullptr, 2};
 }
 
+// The interaction-picture RK4 of cme_rk4ip.hip (its step is written out
+// there) on the same transforms and layout.  The per-mode factor
+// D = exp((-kappa/2 + i omega') h/2) is formed once per launch (FP64, then
+// rounded) into the third workspace vector; the detuning phase is one scalar
+// per half step.  Per stage, from the stage's N(u) = q:
+//   stage 1: yI = P1 y, k1 = P1 q   -> the state array holds yI, W1 = k1
+//   stage 2: k2 = q                 -> W2 = k2
+//   stage 3: k3 = q                 -> W1 = Q = yI + h/6 (k1 + 2 k2 + 2 k3),
+//                                      next input P2 (yI + h k3)
+//   stage 4: y' = P2 Q + h/6 q      -> the state array
+// (P1 = D exp(-i int_t0^tm sigma), P2 = D exp(-i int_tm^t1 sigma)): 224 bytes
+// of global traffic per mode and step in FP64.
+template <typename Real, int N, int E, int V, int PS, int D>
+__global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
+    rk4ip_stream(RunArgs a) {
+  constexpr int TP = 0;
+  static_assert(D >= 1, "prefetch distance");
+  using SH = WaveShape<Real, N, E, V, PS, TP>;
+  using WP = WavePlan<N, E, V, TP>;
+  static_assert(WP::W > 1 && SH::IPB == 1, "one instance per workgroup");
+  static_assert(WP::Q == 1, "one cross-wave element per slot");
+  __shared__ cx<Real> lds[SH::PER_INST];
+
+  const int lane = (int)threadIdx.x & 63;
+  const int w = (int)threadIdx.x >> 6;
+  const int slot = (int)blockIdx.x;
+  const int id = a.order[slot];
+  const DevInst d = a.inst[id];
+  cx<Real> *X = lds;
+  cx<Real> *Y = SH::TWO ? X + SH::WV * SH::LB1 : X;
+  cx<Real> *A = reinterpret_cast<cx<Real> *>(a.A) + d.offset;
+  constexpr int CB = (int)sizeof(cx<Real>);
+  const __amdgpu_buffer_rsrc_t rA = buf_rsrc(A, N * CB);
+  cx<Real> *work = reinterpret_cast<cx<Real> *>(a.work) + (int64_t)slot * 3 * N;
+  const __amdgpu_buffer_rsrc_t rW1 = buf_rsrc(work, N * CB);
+  const __amdgpu_buffer_rsrc_t rW2 = buf_rsrc(work + N, N * CB);
+  const __amdgpu_buffer_rsrc_t rD = buf_rsrc(work + 2 * N, N * CB);
+  const int i0 = lane + 64 * w;  // slot m: mode i0 + N1 m
+
+  StreamTw<N, E, V, true, Real> tw;
+  load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+
+  const double h = a.h;
+  cx<Real> v[E];
+  {
+    const __amdgpu_buffer_rsrc_t rK = buf_rsrc(a.kappa + d.offset, N * 8);
+    const __amdgpu_buffer_rsrc_t rO = buf_rsrc(a.omega + d.offset, N * 8);
+    sfor<0, E>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      const double mag = exp(-0.25 * h * buf_load<double>(rK, 8 * i0, 8 * WP::N1 * m));
+      double sn, cs;
+      sincos(0.5 * h * buf_load<double>(rO, 8 * i0, 8 * WP::N1 * m), &sn, &cs);
+      buf_store(cx<Real>{(Real)(mag * cs), (Real)(mag * sn)}, rD, CB * i0, CB * WP::N1 * m);
+      v[m] = buf_load<cx<Real>>(rA, CB * i0, CB * WP::N1 * m);
+    });
+  }
+  const bool pump_owner = (w == 0 && lane == 0);  // mode N/2 sits in slot E/2 there
+  const Real gn = (Real)d.g0n;
+  const cx<Real> pump = {(Real)d.pump_re, (Real)d.pump_im};
+  const Real hh = (Real)(0.5 * h), hf = (Real)h, h6 = (Real)(h / 6.0), two = (Real)2;
+  cx<Real> *ckpt = reinterpret_cast<cx<Real> *>(a.ckpt);
+  int32_t to_ckpt = a.ckpt_every;
+  int64_t ckpt_slot = 0;
+  bool bad = false;
+
+  for (int64_t n = 0; n < a.n_steps; ++n) {
+    const double t0 = (double)(a.step0 + n) * h, tm = t0 + 0.5 * h, t1 = t0 + h;
+    double sn, cs;
+    sincos(-sigma_integral(d.sigma0, d.sigma1, d.tau_ramp, t0, tm), &sn, &cs);
+    const cx<Real> c1 = {(Real)cs, (Real)sn};
+    sincos(-sigma_integral(d.sigma0, d.sigma1, d.tau_ramp, tm, t1), &sn, &cs);
+    const cx<Real> c2 = {(Real)cs, (Real)sn};
+    sfor<0, 4>([&](auto si) {
+      constexpr int s = decltype(si)::value;
+      stream_fwdpath<N, E, V, +1, PS, !SH::TWO, true>(v, X, tw, w, lane);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
+        v[m] = {p * v[m].re, p * v[m].im};
+      });
+      stream_backpath<N, E, V, -1, PS, true>(v, X, Y, tw, w, lane);
+      struct Ops {
+        cx<Real> y, w1, w2, dm;
+      };
+      Ops ring[D];
+      __builtin_amdgcn_sched_barrier(0);  // no operand load above the transforms
+      auto fetch = [&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        constexpr int off = CB * WP::N1 * m;
+        Ops &o = ring[m % D];
+        if constexpr (s < 3) o.y = buf_load<cx<Real>>(rA, CB * i0, off);  // y, then yI
+        if constexpr (s != 1) o.dm = buf_load<cx<Real>>(rD, CB * i0, off);
+        if constexpr (s >= 2) o.w1 = buf_load<cx<Real>>(rW1, CB * i0, off);
+        if constexpr (s == 2) o.w2 = buf_load<cx<Real>>(rW2, CB * i0, off);
+      };
+      sfor<0, (D < E ? D : E)>(fetch);
+      sfor<0, E>([&](auto mi) {
+        constexpr int m = decltype(mi)::value;
+        __builtin_amdgcn_sched_barrier(0);
+        const Ops o = ring[m % D];
+        if constexpr (m + D < E) fetch(ic<m + D>{});
+        constexpr int off = CB * WP::N1 * m;
+        cx<Real> q = {-gn * v[m].im, gn * v[m].re};  // N(u) = i (g0/N) N K + pump
+        if constexpr (m == E / 2) {
+          if (pump_owner) q = cadd(q, pump);
+        }
+        if constexpr (s == 0) {
+          const cx<Real> p1 = cmul(o.dm, c1);
+          const cx<Real> k1 = cmul(p1, q), yi = cmul(p1, o.y);
+          buf_store(yi, rA, CB * i0, off);
+          buf_store(k1, rW1, CB * i0, off);
+          v[m] = {yi.re + hh * k1.re, yi.im + hh * k1.im};
+        } else if constexpr (s == 1) {
+          buf_store(q, rW2, CB * i0, off);
+          v[m] = {o.y.re + hh * q.re, o.y.im + hh * q.im};
+        } else if constexpr (s == 2) {
+          cx<Real> acc = {o.w1.re + two * o.w2.re, o.w1.im + two * o.w2.im};
+          acc = {acc.re + two * q.re, acc.im + two * q.im};
+          buf_store(cx<Real>{o.y.re + h6 * acc.re, o.y.im + h6 * acc.im}, rW1, CB * i0, off);
+          v[m] = cmul(cmul(o.dm, c2), cx<Real>{o.y.re + hf * q.re, o.y.im + hf * q.im});
+        } else {
+          const cx<Real> z = cmul(cmul(o.dm, c2), o.w1);
+          v[m] = {z.re + h6 * q.re, z.im + h6 * q.im};
+          buf_store(v[m], rA, CB * i0, off);
+          if (ckpt != nullptr && to_ckpt == 1)
+            ckpt[ckpt_slot * a.total + d.offset + i0 + WP::N1 * m] = v[m];
+          if (n + 1 == a.n_steps) bad |= !(isfinite(v[m].re) && isfinite(v[m].im));
+        }
+      });
+      __builtin_amdgcn_sched_barrier(0);
+    });
+    if (ckpt != nullptr && --to_ckpt == 0) {
+      to_ckpt = a.ckpt_every;
+      ++ckpt_slot;
+    }
+  }
+  if (bad) atomicOr(&a.flags[id], 1);
+}
+
+template <typename Real, int N, int E, int V, int PS, int D>
+hipError_t launch_stream_ip_fwd(const RunArgs &a, hipStream_t st) {
+  using SH = WaveShape<Real, N, E, V, PS, 0>;
+  if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
+  if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
+  hipLaunchKernelGGL((rk4ip_stream<Real, N, E, V, PS, D>), dim3(a.count), dim3(SH::THREADS), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+// kind 14; three complex values of class workspace per mode (W1, W2 and the
+// per-mode factor D); no reverse sweep.  The tuning field holds D.
+template <typename Real, int N, int E, int V, int PS, int D>
+constexpr Variant stream_ip_variant() {
+  using SH = WaveShape<Real, N, E, V, PS, 0>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D, 14, SH::IPB,
+                 SH::THREADS, SH::LDS_BYTES, &launch_stream_ip_fwd<Real, N, E, V, PS, D>, nullptr,
+                 3};
+}
+
 // The first of each precision is the default.  Measured, us per step for 1,
 // 100 and 128 instances with per-mode kappa (kappa the same for every mode):
 // FP64 OR PB D = 1 52.1 / 56.7 / 57.8 (49.0 / 53.6 / 55.7; 255 VGPRs, no
@@ -433,6 +592,11 @@ constexpr Variant stream_variant() {
 // 39.2 / 39.9 (34.7 / 35.5 / 36.3), D = 4 41.8 / 42.8 / 43.6 (38.2 / 39.2 /
 // 39.7).  The stage arithmetic's global-memory traffic is streamed by one CU
 // at about 57 bytes per clock; the transforms alone take about 40 us (FP64).
+// Interaction picture (kind 14), us per step for 1 / 16 / 64 / 128
+// instances, per-mode kappa: FP64 D = 2 49.9 / 50.4 / 51.6 / 56.4, D = 1
+// 50.4 / 50.8 / 53.8 / 58.6 (the staged interaction-picture kernels: 58.5 /
+// 63.5 / 78.9 / 96.8; repeated runs move each figure by up to 2 us); FP32
+// D = 4 35.9 / 35.9 / 36.1 / 36.4, D = 2 35.9 / 35.9 / 36.1 / 36.9.
 static const Variant kStreamVariants[] = {
     stream_variant<double, 8192, 16, 2, 3, 1, true, false, true>(),
     stream_variant<double, 8192, 16, 2, 3, 2, true, false, true>(),
@@ -442,6 +606,10 @@ static const Variant kStreamVariants[] = {
     stream_variant<float, 8192, 16, 2, 3, 2, true, true, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, true, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, false>(),
+    stream_ip_variant<double, 8192, 16, 2, 3, 2>(),
+    stream_ip_variant<double, 8192, 16, 2, 3, 1>(),
+    stream_ip_variant<float, 8192, 16, 2, 3, 4>(),
+    stream_ip_variant<float, 8192, 16, 2, 3, 2>(),
 };
 
 const Variant *variants_stream(int *count) {

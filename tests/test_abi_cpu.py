@@ -62,7 +62,7 @@ def test_kernel_table_covers_every_size():
                 assert info["threads"] % 64 == 0
             else:
                 assert info["threads"] == info["instances_per_group"] * (n // e)
-            if info["kind"] in (1, 2, 3, 4, 5, 7, 11, 12, 13):  # two-level: whole wavefronts per instance
+            if info["kind"] in (1, 2, 3, 4, 5, 7, 11, 12, 13, 14):  # two-level: whole wavefronts per instance
                 assert (n // e) % 64 == 0
             seen.add(k)
         # above 8192 only the staged kernels

@@ -168,7 +168,7 @@ def _ip_params(precision):
     try:
         from paper_1307_3428_amd import cme as C
         return [(n, k) for n in (128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768, 65536)
-                for k in C.cme_list_kernels(precision, n) if C.cme_kernel_info(k)["kind"] in (7, 8, 12)]
+                for k in C.cme_list_kernels(precision, n) if C.cme_kernel_info(k)["kind"] in (7, 8, 12, 14)]
     except Exception:
         return [(128, 0)]
 
