@@ -413,8 +413,10 @@ int adjoint_streams(cme_plan *p) {
   return CME_OK;
 }
 
-// Time every compiled variant of each size once on plan-owned zero state and
-// keep the fastest.  Runs at init on the plan's stream.
+// Time every compiled variant of each size on plan-owned zero state and keep
+// the fastest: two short warm-up launches per variant, then two round-robin
+// passes of one launch of about 8 ms per variant, the faster pass counting.
+// Runs at init on the plan's stream.
 int autotune(cme_plan *p) {
   void *state = nullptr;
   const size_t bytes = p->elem * (size_t)p->total;
@@ -423,34 +425,60 @@ int autotune(cme_plan *p) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = CME_EHIP;
   if (rc == CME_OK && hipMemsetAsync(state, 0, bytes, p->stream) != hipSuccess) rc = CME_EHIP;
+  // one launch of n steps of variant v, its time in ms (< 0: HIP error)
+  auto timed = [&](SizeClass &c, const Variant *v, int64_t n) -> float {
+    SizeClass tmp = c;
+    tmp.var = v;
+    const cme::RunArgs a = run_args(p, tmp, state, 0, n, 0, nullptr, nullptr);
+    float ms = 0.f;
+    if (hipEventRecord(e0, p->stream) != hipSuccess || v->fwd(a, p->stream) != hipSuccess ||
+        hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return -1.f;
+    return ms;
+  };
   for (auto &c : p->classes) {
     if (rc != CME_OK) break;
-    float best = 1e30f;
-    const Variant *pick = c.var;
-    // enough steps for a stable timing, scaled down for large sizes
-    const int64_t steps = std::max<int64_t>(4, (int64_t)(262144 / c.n));
-    // the default first; another variant replaces the best so far only when
-    // it is more than 5% faster, so timing noise does not flip the choice
+    // warm-up length, scaled down for large sizes; the timed launches are
+    // lengthened to about kTuneMs each (single launches of a millisecond
+    // differ by several percent from run to run, more than the variants do)
+    const int64_t base = std::max<int64_t>(4, (int64_t)(262144 / c.n));
+    constexpr float kTuneMs = 8.f;
+    // the default first
     std::vector<const Variant *> order{c.var};
     for (const Variant *v : candidates(p->precision, c.n, p->integrator + 16 * p->fwm))
       if (v != c.var) order.push_back(v);
-    for (const Variant *v : order) {
-      if ((rc = ensure_work(p, c, v)) != CME_OK) break;
-      SizeClass tmp = c;
-      tmp.var = v;
-      const cme::RunArgs a = run_args(p, tmp, state, 0, steps, 0, nullptr, nullptr);
-      float ms = 0.f;
-      if (v->fwd(a, p->stream) != hipSuccess) { rc = CME_EHIP; break; }  // warm-up
-      if (hipEventRecord(e0, p->stream) != hipSuccess) { rc = CME_EHIP; break; }
-      if (v->fwd(a, p->stream) != hipSuccess) { rc = CME_EHIP; break; }
-      if (hipEventRecord(e1, p->stream) != hipSuccess) { rc = CME_EHIP; break; }
-      if (hipEventSynchronize(e1) != hipSuccess) { rc = CME_EHIP; break; }
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = CME_EHIP; break; }
-      if (ms < 0.95f * best) {
-        best = ms;
-        pick = v;
+    std::vector<int64_t> steps(order.size(), base);
+    std::vector<float> per(order.size(), 1e30f);  // ms per step, the faster pass
+    // two passes over all variants: in the first the clock is still rising
+    // and each kernel's first launch also loads its code, so neither the
+    // first variant nor the first launch of any decides alone
+    for (int pass = 0; pass < 2 && rc == CME_OK; ++pass) {
+      for (size_t j = 0; j < order.size(); ++j) {
+        const Variant *v = order[j];
+        if (pass == 0) {
+          if ((rc = ensure_work(p, c, v)) != CME_OK) break;
+          float warm = timed(c, v, base);
+          if (warm >= 0.f) warm = timed(c, v, base);
+          if (warm < 0.f) { rc = CME_EHIP; break; }
+          steps[j] = base * std::min<int64_t>(
+                                64, std::max<int64_t>(1, (int64_t)(kTuneMs / std::max(warm, 1e-3f))));
+        }
+        const float ms = timed(c, v, steps[j]);
+        if (ms < 0.f) { rc = CME_EHIP; break; }
+        per[j] = std::min(per[j], ms / (float)steps[j]);
       }
     }
+    if (rc != CME_OK) break;
+    // another variant replaces the best so far only when it is more than 5%
+    // faster, so timing noise does not flip the choice
+    float best = 1e30f;
+    const Variant *pick = c.var;
+    for (size_t j = 0; j < order.size(); ++j)
+      if (per[j] < 0.95f * best) {
+        best = per[j];
+        pick = order[j];
+      }
     c.var = pick;
   }
   if (e0) (void)hipEventDestroy(e0);

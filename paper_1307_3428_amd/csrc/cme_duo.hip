@@ -33,7 +33,8 @@ namespace cme {
 
 // Butterflies of pass p of the wave-local transform of sign S on v (twiddles
 // t[r] = b^r of the pass), results back in v: v[q + r Qb] = Z_r of butterfly q.
-template <int N, int E, int S, int p, typename Real>
+// FMA: t holds the level twiddles of dft_reg_fma in place of the powers.
+template <int N, int E, int S, int p, bool FMA = false, typename Real>
 __device__ __forceinline__ void lean_compute(cx<Real> (&v)[E], const cx<Real> *t) {
   using PL = typename LeanPlan<N, E>::Sub;
   constexpr int R = PL::radix(p), NSp = PL::ns(p), Qb = E / R;
@@ -41,13 +42,17 @@ __device__ __forceinline__ void lean_compute(cx<Real> (&v)[E], const cx<Real> *t
     constexpr int q = decltype(qi)::value;
     cx<Real> z[R];
     sfor<0, R>([&](auto ri) { z[decltype(ri)::value] = v[q + decltype(ri)::value * Qb]; });
-    if constexpr (NSp > 1) {
-      sfor<1, R>([&](auto ri) {
-        constexpr int r = decltype(ri)::value;
-        z[r] = ctw<S>(z[r], t[r]);
-      });
+    if constexpr (FMA && NSp > 1) {
+      dft_reg_fma<R, S>(z, t);
+    } else {
+      if constexpr (NSp > 1) {
+        sfor<1, R>([&](auto ri) {
+          constexpr int r = decltype(ri)::value;
+          z[r] = ctw<S>(z[r], t[r]);
+        });
+      }
+      dft_reg<R, S>(z);
     }
-    dft_reg<R, S>(z);
     sfor<0, R>([&](auto ri) { v[q + decltype(ri)::value * Qb] = z[decltype(ri)::value]; });
   });
 }
@@ -139,6 +144,66 @@ __device__ __forceinline__ void load_full_twiddles(FullTw<N, E, Real> &tw,
   }
 }
 
+// FT = 2, the multiply-add form: the level twiddles of dft_reg_fma for each
+// pass p >= 1 (entry half + kk for the level of length 2 half: w =
+// b_p^(R / len) exp(-2 pi i kk / len)), and the cross-wave twiddles of each
+// group i of the thread's elements with the group's rotation folded in
+// (b_x^r exp(-2 pi i r i / (N / 64)) = tab[r (n1 + 64 i)]), so that each is
+// one complex multiply.
+// XG = false: one set of cross-wave powers for all groups (the rotation of
+// each group applied on use), for kernels without the registers to spare.
+template <int N, int E, typename Real, bool XG = true> struct FmaTw {
+  using LP = LeanPlan<N, E>;
+  using PL = typename LP::Sub;
+  cx<Real> sub[PL::P][E];
+  cx<Real> x[XG ? LP::Q : 1][(LP::WV > 1 ? LP::WV : 1)];
+};
+
+template <int N, int E, bool XG, typename Real>
+__device__ __forceinline__ void load_fma_twiddles(FmaTw<N, E, Real, XG> &tw,
+                                                  const cx<Real> *__restrict__ tab, int w,
+                                                  int l) {
+  using LP = LeanPlan<N, E>;
+  using PL = typename LP::Sub;
+  constexpr int TS = LP::WV;
+  sfor<1, PL::P>([&](auto pi) {
+    constexpr int p = decltype(pi)::value;
+    constexpr int R = PL::radix(p), NSp = PL::ns(p);
+    constexpr int STRIDE = LP::N1 / (NSp * R);
+    const int k = l & (NSp - 1);
+    sfor<1, ilog2(R) + 1>([&](auto lv) {
+      constexpr int len = 1 << decltype(lv)::value, half = len / 2;
+      sfor<0, half>([&](auto kki) {
+        constexpr int kk = decltype(kki)::value;
+        tw.sub[p][half + kk] =
+            fma_form(tab[((R / len) * k * STRIDE * TS + kk * (N / len)) & (N - 1)]);
+      });
+    });
+  });
+  if constexpr (LP::WV > 1) {
+    const int n1 = l + 64 * w * LP::Q;
+    sfor<0, (XG ? LP::Q : 1)>([&](auto ii) {
+      constexpr int i = decltype(ii)::value;
+      sfor<1, LP::WV>([&](auto ri) {
+        constexpr int r = decltype(ri)::value;
+        tw.x[i][r] = tab[(r * (n1 + 64 * i)) & (N - 1)];
+      });
+    });
+  }
+}
+
+// IsFmaTw: the multiply-add pass twiddles; CombTw: cross-wave twiddles per group
+template <typename TW> struct IsFmaTw : std::false_type {};
+template <int N, int E, typename Real, bool XG>
+struct IsFmaTw<FmaTw<N, E, Real, XG>> : std::true_type {};
+template <typename TW> struct CombTw : std::false_type {};
+template <int N, int E, typename Real> struct CombTw<FmaTw<N, E, Real, true>> : std::true_type {};
+
+template <int N, int E, bool XG, typename Real>
+__device__ __forceinline__ void load_twiddle_source(FmaTw<N, E, Real, XG> &tw, const cx<Real> *tab,
+                                                    int w, int l) {
+  load_fma_twiddles<N, E>(tw, tab, w, l);
+}
 template <int N, int E, typename Real>
 __device__ __forceinline__ void load_twiddle_source(LeanTw<N, E, Real> &tw, const cx<Real> *tab,
                                                     int w, int l) {
@@ -159,14 +224,31 @@ template <int p, int R, int N, int E, typename Real>
 __device__ __forceinline__ void pass_twiddles(cx<Real> (&t)[R], const FullTw<N, E, Real> &tw) {
   sfor<1, R>([&](auto ri) { t[decltype(ri)::value] = tw.sub[p][decltype(ri)::value]; });
 }
-// t[r] = power r of the cross-wave twiddle base
-template <int WV, int N, int E, typename Real>
-__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[WV], const LeanTw<N, E, Real> &tw) {
-  pow_fill<WV>(t, tw.x[0]);
+template <int p, int R, int N, int E, bool XG, typename Real>
+__device__ __forceinline__ void pass_twiddles(cx<Real> (&t)[R], const FmaTw<N, E, Real, XG> &tw) {
+  sfor<1, R>([&](auto ri) { t[decltype(ri)::value] = tw.sub[p][decltype(ri)::value]; });
 }
-template <int WV, int N, int E, typename Real>
-__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[WV], const FullTw<N, E, Real> &tw) {
-  sfor<1, WV>([&](auto ri) { t[decltype(ri)::value] = tw.x[decltype(ri)::value]; });
+// t[i][r] = cross-wave twiddle power r for group i: the same base powers for
+// every group (the group's rotation is applied on use), or with FmaTw the
+// group's own twiddles
+template <int Q, int WV, int N, int E, typename Real>
+__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[Q][WV], const LeanTw<N, E, Real> &tw) {
+  pow_fill<WV>(t[0], tw.x[0]);
+  sfor<1, Q>([&](auto ii) { sfor<1, WV>([&](auto ri) {
+    t[decltype(ii)::value][decltype(ri)::value] = t[0][decltype(ri)::value]; }); });
+}
+template <int Q, int WV, int N, int E, typename Real>
+__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[Q][WV], const FullTw<N, E, Real> &tw) {
+  sfor<0, Q>([&](auto ii) { sfor<1, WV>([&](auto ri) {
+    t[decltype(ii)::value][decltype(ri)::value] = tw.x[decltype(ri)::value]; }); });
+}
+template <int Q, int WV, int N, int E, bool XG, typename Real>
+__device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[Q][WV],
+                                               const FmaTw<N, E, Real, XG> &tw) {
+  sfor<0, Q>([&](auto ii) { sfor<1, WV>([&](auto ri) {
+    t[decltype(ii)::value][decltype(ri)::value] =
+        tw.x[XG ? decltype(ii)::value : 0][decltype(ri)::value];
+  }); });
 }
 
 // The passes of two independent wave-local transforms of sign S, a in region
@@ -180,6 +262,7 @@ __device__ __forceinline__ void pair_passes(cx<Real> (&va)[E], cx<Real> (&vb)[E]
                                             cx<Real> *rb, const TW &tw, int l) {
   using LP = LeanPlan<N, E>;
   using PL = typename LP::Sub;
+  constexpr bool FMA = IsFmaTw<TW>::value;
   sfor<0, PL::P - 1>([&](auto pi) {
     constexpr int p = decltype(pi)::value;
     constexpr int R = PL::radix(p), R1 = PL::radix(p + 1);
@@ -188,14 +271,14 @@ __device__ __forceinline__ void pair_passes(cx<Real> (&va)[E], cx<Real> (&vb)[E]
     lean_scatter<N, E, PS, p>(va, ra, l);
     wave_fence();  // scatter before gather (other lanes' values)
     lean_gather<PS>(va, ra, l);
-    lean_compute<N, E, S, p>(vb, t);
+    lean_compute<N, E, S, p, FMA>(vb, t);
     // a pass without twiddles has about half the VALU work
     interleave_ds_valu<2 * E, (PL::ns(p) > 1 ? NV : NV / 2)>();
     pass_twiddles<p + 1>(t1, tw);
     lean_scatter<N, E, PS, p>(vb, rb, l);
     wave_fence();
     lean_gather<PS>(vb, rb, l);
-    lean_compute<N, E, S, p + 1>(va, t1);
+    lean_compute<N, E, S, p + 1, FMA>(va, t1);
     interleave_ds_valu<2 * E, NV>();
   });
 }
@@ -207,14 +290,28 @@ __device__ __forceinline__ void lean_compute_last(cx<Real> (&v)[E], const TW &tw
   constexpr int PL1 = PL::P - 1, RL = PL::radix(PL1);
   cx<Real> tl[RL];
   pass_twiddles<PL1>(tl, tw);
-  lean_compute<N, E, S, PL1>(v, tl);
+  lean_compute<N, E, S, PL1, IsFmaTw<TW>::value>(v, tl);
 }
 
 // Cross-wave compute of the forward path (WV-point DFTs over n2 and
 // twiddles) for one sequence, in place in v.
-template <int N, int E, int S, typename Real>
-__device__ __forceinline__ void lean_cross_dft(cx<Real> (&v)[E],
-                                               const cx<Real> (&t)[(LeanPlan<N, E>::WV)]) {
+// COMB: t[i] already holds group i's rotation.
+template <int N, int E, int S, bool COMB, int I, typename Real>
+__device__ __forceinline__ void lean_cross_tw(cx<Real> (&z)[(LeanPlan<N, E>::WV)],
+                                              const cx<Real> (&t)[(LeanPlan<N, E>::WV)]) {
+  if constexpr (COMB) {
+    sfor<1, LeanPlan<N, E>::WV>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      z[r] = ctw<S>(z[r], t[r]);
+    });
+  } else {
+    cross_twiddle<N, E, S, I>(z, t);
+  }
+}
+
+template <int N, int E, int S, bool COMB, typename Real>
+__device__ __forceinline__ void lean_cross_dft(
+    cx<Real> (&v)[E], const cx<Real> (&t)[(LeanPlan<N, E>::Q)][(LeanPlan<N, E>::WV)]) {
   using LP = LeanPlan<N, E>;
   constexpr int WV = LP::WV, Q = LP::Q;
   sfor<0, Q>([&](auto ii) {
@@ -222,7 +319,7 @@ __device__ __forceinline__ void lean_cross_dft(cx<Real> (&v)[E],
     cx<Real> z[WV];
     sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[i + Q * decltype(ri)::value]; });
     dft_reg<WV, S>(z);
-    cross_twiddle<N, E, S, i>(z, t);
+    lean_cross_tw<N, E, S, COMB, i>(z, t[i]);
     sfor<0, WV>([&](auto ri) { v[i + Q * decltype(ri)::value] = z[decltype(ri)::value]; });
   });
 }
@@ -260,16 +357,16 @@ __device__ __forceinline__ void lean_cross_gather(cx<Real> (&v)[E], const cx<Rea
 }
 
 // Cross-wave compute of the back path (twiddles, WV-point DFTs over k2).
-template <int N, int E, int S, typename Real>
-__device__ __forceinline__ void lean_cross_idft(cx<Real> (&v)[E],
-                                                const cx<Real> (&t)[(LeanPlan<N, E>::WV)]) {
+template <int N, int E, int S, bool COMB, typename Real>
+__device__ __forceinline__ void lean_cross_idft(
+    cx<Real> (&v)[E], const cx<Real> (&t)[(LeanPlan<N, E>::Q)][(LeanPlan<N, E>::WV)]) {
   using LP = LeanPlan<N, E>;
   constexpr int WV = LP::WV, Q = LP::Q;
   sfor<0, Q>([&](auto ii) {
     constexpr int i = decltype(ii)::value;
     cx<Real> z[WV];
     sfor<0, WV>([&](auto ri) { z[decltype(ri)::value] = v[i + Q * decltype(ri)::value]; });
-    cross_twiddle<N, E, S, i>(z, t);
+    lean_cross_tw<N, E, S, COMB, i>(z, t[i]);
     dft_reg<WV, S>(z);
     sfor<0, WV>([&](auto ri) { v[i + Q * decltype(ri)::value] = z[decltype(ri)::value]; });
   });
@@ -286,14 +383,15 @@ __device__ __forceinline__ void lean_fwd2(cx<Real> (&va)[E], cx<Real> (&vb)[E], 
   constexpr int WV = LP::WV;
   static_assert(WV > 1, "paired kernels need the cross-wave exchange");
   if constexpr (PRE) __syncthreads();
-  cx<Real> t[WV];
+  constexpr bool COMB = CombTw<TW>::value;
+  cx<Real> t[LP::Q][WV];
   cross_twiddles(t, tw);
   const int c0 = lpad<PS>(l + 64 * w * LP::Q);
   __builtin_amdgcn_sched_barrier(0);
-  lean_cross_dft<N, E, S>(va, t);
+  lean_cross_dft<N, E, S, COMB>(va, t);
   __builtin_amdgcn_sched_barrier(0);
   lean_cross_scatter<N, E, PS>(va, XA, c0);
-  lean_cross_dft<N, E, S>(vb, t);
+  lean_cross_dft<N, E, S, COMB>(vb, t);
   interleave_ds_valu<E, NV>();
   lean_cross_scatter<N, E, PS>(vb, XB, c0);
   __syncthreads();
@@ -335,15 +433,16 @@ __device__ __forceinline__ void lean_back2(cx<Real> (&va)[E], cx<Real> (&vb)[E],
     XB[lpad_off<PS, 64 * m, false>(g0)] = vb[m];
   });
   __syncthreads();
-  cx<Real> t[WV];
+  constexpr bool COMB = CombTw<TW>::value;
+  cx<Real> t[LP::Q][WV];
   cross_twiddles(t, tw);
   const int c0 = lpad<PS>(l + 64 * w * LP::Q);
   lean_cross_gather<N, E, PS>(va, XA, c0);
   __builtin_amdgcn_sched_barrier(0);
   lean_cross_gather<N, E, PS>(vb, XB, c0);
-  lean_cross_idft<N, E, S>(va, t);
+  lean_cross_idft<N, E, S, COMB>(va, t);
   interleave_ds_valu<E, NV>();
-  lean_cross_idft<N, E, S>(vb, t);
+  lean_cross_idft<N, E, S, COMB>(vb, t);
 }
 
 template <typename Real, int N, int E, int PS> struct DuoShape {
@@ -379,7 +478,10 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   const double *kap = a.kappa + d.offset;
   const double *omg = a.omega + d.offset;
 
-  std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
+  std::conditional_t<
+      FT >= 2, FmaTw<N, E, Real, FT == 2>,
+      std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>>>
+      tw;
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> y[E], yw[E], va[E], vb[E];
@@ -560,7 +662,10 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
   cx<Real> *gA = reinterpret_cast<cx<Real> *>(a.gA) + d.offset;
   const cx<Real> *stages = reinterpret_cast<const cx<Real> *>(a.stages);
 
-  std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>> tw;
+  std::conditional_t<
+      FT >= 2, FmaTw<N, E, Real, FT == 2>,
+      std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>>>
+      tw;
   load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> yb1[E], yb[E], k2[E], va[E], vb[E], ra[E], rb[E];
@@ -746,24 +851,28 @@ hipError_t launch_lean_adj(const AdjArgs &a, hipStream_t st);
 
 // NV: VALU instructions scheduled after each LDS instruction of the other
 // sequence (reported as the variant's exchange field)
-// FT: twiddles formed from one base per pass (0) or all powers held in
-// registers (1); reported as exchange = NV + 16 FT.  The reverse sweep holds
-// all powers in registers too (it reads the stage records in the same slot
-// order whatever the forward kernel's twiddle source).
+// FT: twiddles formed from one base per pass (0), all powers held in
+// registers (1), or the level twiddles of the multiply-add form and the
+// cross-wave twiddles of each element group held in registers (2); reported
+// as exchange = NV + 16 FT.  The reverse sweep holds all powers in registers
+// (FT = 1), or for an FT = 2 kernel the multiply-add level twiddles with one
+// set of cross-wave powers (3: the per-group ones would spill it); it reads
+// the stage records in the same slot order whatever the forward kernel's
+// twiddle source.
 // Reverse sweep of a paired forward kernel: the paired reverse, except at
 // eight wavefronts per instance (N = 4096), where its registers do not fit
 // two waves per SIMD and the lean reverse, which reads the same stage
 // records, is used.
-template <typename Real, int N, int E, int PS, int NV> constexpr AdjLaunch duo_adj_ptr() {
+template <typename Real, int N, int E, int PS, int NV, int FT> constexpr AdjLaunch duo_adj_ptr() {
   if constexpr (N / (64 * E) >= 8) return &launch_lean_adj<Real, N, E, PS>;
-  else return &launch_duo_adj<Real, N, E, PS, NV, 1>;
+  else return &launch_duo_adj<Real, N, E, PS, NV, FT == 2 ? 3 : 1>;
 }
 
 template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant duo_variant() {
   using SH = DuoShape<Real, N, E, PS>;
   if constexpr (std::is_same<Real, double>::value)
     return Variant{0, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
-                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, duo_adj_ptr<Real, N, E, PS, NV>(), 0,
+                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, duo_adj_ptr<Real, N, E, PS, NV, FT>(), 0,
                    N / (64 * E) < 8 ? 1 : 0};
   else  // FP32 plans have no adjoint
     return Variant{1, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
@@ -775,9 +884,14 @@ template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant
 // faster than the previous defaults at 256 instances); N = 4096 runs eight
 // wavefronts per instance, two per SIMD, with the twiddles rebuilt on use
 // (the register-held tables do not fit), 5% faster than the lean kernel.
+// N = 2048 uses the multiply-add form (FT = 2): 2747 VALU instructions per
+// wave and step in place of 2967, 466.6 against 474.9 ms for 5e4 steps of
+// 256 instances (FP32 7.42 against 7.94 us per step); at N = 1024 (radix-4
+// passes) it saves 7% of the instructions and no time, so it is not built.
 static const Variant kDuoVariants[] = {
     duo_variant<double, 512, 4, 2, 4, 1>(),  duo_variant<double, 1024, 4, 2, 5, 1>(),
     duo_variant<double, 1024, 4, 2, 4, 1>(), duo_variant<double, 1024, 8, 3, 4, 1>(),
+    duo_variant<double, 2048, 8, 3, 5, 2>(), duo_variant<double, 2048, 8, 3, 4, 2>(),
     duo_variant<double, 2048, 8, 3, 5, 1>(), duo_variant<double, 2048, 8, 3, 4, 1>(),
     duo_variant<double, 2048, 8, 3, 4, 0>(), duo_variant<double, 4096, 8, 3, 4, 0>(),
     duo_variant<double, 4096, 8, 3, 5, 0>(),
@@ -790,6 +904,7 @@ static const Variant kDuoVariants[] = {
 static const Variant kDuoVariantsF32[] = {
     duo_variant<float, 512, 4, 2, 4, 1>(),  duo_variant<float, 1024, 4, 2, 5, 1>(),
     duo_variant<float, 1024, 4, 2, 4, 1>(), duo_variant<float, 1024, 8, 3, 5, 1>(),
+    duo_variant<float, 2048, 8, 3, 5, 2>(), duo_variant<float, 2048, 8, 3, 4, 2>(),
     duo_variant<float, 2048, 8, 3, 5, 1>(), duo_variant<float, 2048, 8, 3, 4, 1>(),
 };
 

@@ -181,6 +181,57 @@ __device__ __forceinline__ void dft_reg(cx<Real> (&z)[R]) {
   }
 }
 
+// Fused multiply-add a * b + c in the type's own precision.
+__device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// A twiddle w in the multiply-add form (c, t) with w = c (1 + i t).  Where
+// Re w is zero (w = +-i) c is a tiny positive number and t = Im w / c, so
+// that c t = Im w and c u stays the product to rounding for any operand far
+// below the overflow threshold.
+template <typename Real> __device__ __forceinline__ cx<Real> fma_form(cx<Real> w) {
+  constexpr Real tiny = sizeof(Real) == 8 ? (Real)0x1p-500 : (Real)0x1p-60;
+  const Real c = fabs(w.re) < tiny ? tiny : w.re;
+  return {c, w.im / c};
+}
+
+// Radix-2 butterfly a, x -> a + w x, a - w x with w = c (1 + i t) given as
+// ct = (c, t), or conj(w) for S > 0: u = x (1 + i t), then a +- c u, six
+// fused multiply-adds in place of a complex multiply and four adds.
+template <int S, typename Real>
+__device__ __forceinline__ void fma_bfly(cx<Real> &a, cx<Real> &x, cx<Real> ct) {
+  const Real t = S < 0 ? ct.im : -ct.im;
+  const Real ur = fmar(-t, x.im, x.re), ui = fmar(t, x.re, x.im);
+  x = {fmar(-ct.re, ur, a.re), fmar(-ct.re, ui, a.im)};
+  a = {fmar(ct.re, ur, a.re), fmar(ct.re, ui, a.im)};
+}
+
+// Z_k = sum_r z_r (b^r exp(S 2 pi i r k / R)) for R a power of two, with b
+// (conj(b) for S > 0) the pass's twiddle base: the radix-2
+// decimation-in-time DFT of the twiddled inputs.  The butterflies of the
+// level of length len combine two sub-sequences whose common factors differ
+// by b^(R / len), so that factor joins the level's rotation:
+// w = b^(R / len) exp(-2 pi i kk / len) for butterfly kk < len / 2, held at
+// ct[len / 2 + kk] in the multiply-add form.
+template <int R, int S, typename Real>
+__device__ __forceinline__ void dft_reg_fma(cx<Real> (&z)[R], const cx<Real> *ct) {
+  constexpr int B = ilog2(R);
+  cx<Real> w[R];
+  sfor<0, R>([&](auto i) { w[bitrev(decltype(i)::value, B)] = z[decltype(i)::value]; });
+  sfor<1, B + 1>([&](auto lv) {
+    constexpr int len = 1 << decltype(lv)::value;
+    constexpr int half = len / 2;
+    sfor<0, R / len>([&](auto g) {
+      constexpr int base = decltype(g)::value * len;
+      sfor<0, half>([&](auto kk) {
+        constexpr int k = decltype(kk)::value;
+        fma_bfly<S>(w[base + k], w[base + k + half], ct[half + k]);
+      });
+    });
+  });
+  sfor<0, R>([&](auto i) { z[decltype(i)::value] = w[decltype(i)::value]; });
+}
+
 // ---------------------------------------------------------------------------
 // Pass plan for length N with E elements per thread
 // ---------------------------------------------------------------------------
