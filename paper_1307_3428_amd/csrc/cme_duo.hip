@@ -445,11 +445,268 @@ __device__ __forceinline__ void lean_back2(cx<Real> (&va)[E], cx<Real> (&vb)[E],
   lean_cross_idft<N, E, S, COMB>(vb, t);
 }
 
-template <typename Real, int N, int E, int PS> struct DuoShape {
+// ---------------------------------------------------------------------------
+// N = 2048 as 8 x 256 (LY = 1).  Thread c = 64 w + l holds modes c + 256 m.
+// The inverse path takes the 8-point DFT over its own slots (the three top
+// index bits), twiddles w^(c k1), and writes region k1 at position c; after
+// the barrier the 8 regions are two 256-point sub-transforms per wave, on
+// alternate lanes (lane = 2 t + s, region k1 = 2 w + s, thread t holds
+// positions t + 32 m).  A sub-transform is three Stockham passes, radix 8, 8
+// and 4: one exchange through the wave's own regions, and one, after the
+// second pass, that moves data only between lanes whose index differs in
+// bits 4 and 5, done with v_permlane16_swap / v_permlane32_swap in
+// registers.  Against the two-level layout (a 4-point cross step, one
+// 512-point sub-transform per wave with two LDS exchanges) a transform takes
+// two LDS exchanges instead of three.  The forward path runs the same
+// sub-transform, writes its own regions, and after the barrier the thread
+// gathers position c of every region, twiddles and takes the 8-point DFT,
+// which leaves mode c + 256 m in slot m.
+struct D8 {
+  static constexpr int N = 2048, E = 8, N1 = 256;
+  __device__ static int mode(int w, int l, int m) { return 64 * w + l + 256 * m; }
+};
+// Region length in elements: 256 positions with one pad element every 8
+// (288), plus an offset that starts the regions of alternate lanes 64 bytes
+// apart modulo 128 (FP64 +12, FP32 +8).  Measured at 256 x N=2048 (FP64, us
+// per step): +0 9.50, +4 9.20, +8 9.45, +12 9.12, +16 9.46: 128-byte offsets
+// land on the same LDS banks.
+template <typename Real> struct D8L {
+  static constexpr int RL = 288 + (sizeof(Real) == 8 ? 12 : 8);
+  static constexpr int CTX = 8 * RL;
+};
+
+// cross twiddles x[k1] = exp(-2 pi i c k1 / N); the multiply-add level
+// twiddles of pass 1 (radix 8, base exp(-2 pi i (t mod 8) / 64)) and of the
+// two radix-4 butterflies of pass 2 (bases exp(-2 pi i (t + 32 q) / 256))
+template <typename Real> struct D8Tw {
+  cx<Real> x[8];
+  cx<Real> p1[8];
+  cx<Real> p2[2][4];
+};
+
+// tab[i] = exp(-2 pi i i / 2048)
+template <typename Real>
+__device__ __forceinline__ void load_d8_twiddles(D8Tw<Real> &tw, const cx<Real> *__restrict__ tab,
+                                                 int w, int l) {
+  const int c = 64 * w + l, t = l >> 1;
+  sfor<1, 8>([&](auto ki) {
+    constexpr int k1 = decltype(ki)::value;
+    tw.x[k1] = tab[(c * k1) & (D8::N - 1)];
+  });
+  // level of length len, butterfly kk: b^(R / len) exp(-2 pi i kk / len)
+  auto level = [&](cx<Real> *dst, int R, int bidx) {
+    for (int len = 2, half = 1; len <= R; len *= 2, half *= 2)
+      for (int kk = 0; kk < half; ++kk)
+        dst[half + kk] = fma_form(tab[((R / len) * bidx + kk * (D8::N / len)) & (D8::N - 1)]);
+  };
+  level(tw.p1, 8, 32 * (t & 7));
+  level(tw.p2[0], 4, 8 * t);
+  level(tw.p2[1], 4, 8 * (t + 32));
+}
+template <typename Real>
+__device__ __forceinline__ void load_twiddle_source(D8Tw<Real> &tw, const cx<Real> *tab, int w,
+                                                    int l) {
+  load_d8_twiddles(tw, tab, w, l);
+}
+
+// v_permlane32_swap: the upper 32 lanes of a trade places with the lower 32
+// lanes of b; v_permlane16_swap: the odd rows (16 lanes) of a with the even
+// rows of b
+__device__ __forceinline__ void lane_swap32(double &a, double &b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+__device__ __forceinline__ void lane_swap16(double &a, double &b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+__device__ __forceinline__ void lane_swap32(float &a, float &b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void lane_swap16(float &a, float &b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// The second exchange of a sub-transform.  After pass 1 element r of thread
+// t belongs at position 64 (t >> 3) + 8 r + (t & 7); pass 2 needs positions
+// t' + 32 m in slot m.  Source and destination agree in t & 7; the swap over
+// lane bit 5 trades register bit 1 for t bit 4, the swap over lane bit 4
+// register bit 0 for t bit 3, and slot m is then register 4 (m & 1) +
+// 2 (m >> 2) + ((m >> 1) & 1).
+template <typename Real> __device__ __forceinline__ void d8_lane_exchange(cx<Real> (&v)[8]) {
+  sfor<0, 4>([&](auto ji) {
+    constexpr int r = (decltype(ji)::value & 1) + 4 * (decltype(ji)::value >> 1);  // 0 1 4 5
+    lane_swap32(v[r].re, v[r ^ 2].re);
+    lane_swap32(v[r].im, v[r ^ 2].im);
+  });
+  sfor<0, 4>([&](auto ji) {
+    constexpr int r = 2 * decltype(ji)::value;  // 0 2 4 6
+    lane_swap16(v[r].re, v[r ^ 1].re);
+    lane_swap16(v[r].im, v[r ^ 1].im);
+  });
+  cx<Real> u[8];
+  sfor<0, 8>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    u[m] = v[4 * (m & 1) + 2 * (m >> 2) + ((m >> 1) & 1)];
+  });
+  sfor<0, 8>([&](auto mi) { v[decltype(mi)::value] = u[decltype(mi)::value]; });
+}
+
+// passes 1 and 2 of a sub-transform (pass 2: radix-4 butterflies q = 0, 1 on
+// slots q + 2 s, positions t + 32 q + 64 s), natural order out
+template <int S, typename Real>
+__device__ __forceinline__ void d8_pass1(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+  dft_reg_fma<8, S>(v, tw.p1);
+}
+template <int S, typename Real>
+__device__ __forceinline__ void d8_pass2(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+  sfor<0, 2>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    cx<Real> z[4];
+    sfor<0, 4>([&](auto si) { z[decltype(si)::value] = v[q + 2 * decltype(si)::value]; });
+    dft_reg_fma<4, S>(z, tw.p2[q]);
+    sfor<0, 4>([&](auto si) { v[q + 2 * decltype(si)::value] = z[decltype(si)::value]; });
+  });
+}
+// the first exchange: pass 0 leaves element r at position 8 t + r
+template <typename Real>
+__device__ __forceinline__ void d8_scatter0(const cx<Real> (&v)[8], cx<Real> *R, int t) {
+  const int b = lpad<3>(8 * t);
+  sfor<0, 8>([&](auto ri) { R[b + decltype(ri)::value] = v[decltype(ri)::value]; });
+}
+template <typename Real>
+__device__ __forceinline__ void d8_gather(cx<Real> (&v)[8], const cx<Real> *R, int t) {
+  sfor<0, 8>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    v[m] = R[lpad<3>(t + 32 * m)];
+  });
+}
+template <typename Real>
+__device__ __forceinline__ void d8_put(const cx<Real> (&v)[8], cx<Real> *R, int t) {
+  sfor<0, 8>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    R[lpad<3>(t + 32 * m)] = v[m];
+  });
+}
+// region k1 at position c, for k1 = 0..7
+template <typename Real>
+__device__ __forceinline__ void d8_cross_put(const cx<Real> (&v)[8], cx<Real> *X, int c) {
+  const int o = lpad<3>(c);
+  sfor<0, 8>([&](auto ki) { X[decltype(ki)::value * D8L<Real>::RL + o] = v[decltype(ki)::value]; });
+}
+template <typename Real>
+__device__ __forceinline__ void d8_cross_get(cx<Real> (&v)[8], const cx<Real> *X, int c) {
+  const int o = lpad<3>(c);
+  sfor<0, 8>([&](auto ki) { v[decltype(ki)::value] = X[decltype(ki)::value * D8L<Real>::RL + o]; });
+}
+template <int S, typename Real>
+__device__ __forceinline__ void d8_cross_inv(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+  dft_reg<8, S>(v);
+  sfor<1, 8>([&](auto ki) { v[decltype(ki)::value] = ctw<S>(v[decltype(ki)::value], tw.x[decltype(ki)::value]); });
+}
+template <int S, typename Real>
+__device__ __forceinline__ void d8_cross_fwd(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+  sfor<1, 8>([&](auto ki) { v[decltype(ki)::value] = ctw<S>(v[decltype(ki)::value], tw.x[decltype(ki)::value]); });
+  dft_reg<8, S>(v);
+}
+
+// Two inverse paths (mode order in, sub-transform order out) in contexts XA,
+// XB, the LDS traffic of one sequence interleaved with the other's
+// arithmetic.  PRE: barrier first (single buffer set).
+template <int S, bool PRE, int NV, typename Real>
+__device__ __forceinline__ void d8_inv2(cx<Real> (&va)[8], cx<Real> (&vb)[8], cx<Real> *XA,
+                                        cx<Real> *XB, const D8Tw<Real> &tw, int w, int l) {
+  if constexpr (PRE) __syncthreads();
+  const int c = 64 * w + l, t = l >> 1, reg = (2 * w + (l & 1)) * D8L<Real>::RL;
+  __builtin_amdgcn_sched_barrier(0);
+  d8_cross_inv<S>(va, tw);
+  __builtin_amdgcn_sched_barrier(0);
+  d8_cross_put(va, XA, c);
+  d8_cross_inv<S>(vb, tw);
+  interleave_ds_valu<8, NV>();
+  d8_cross_put(vb, XB, c);
+  __syncthreads();
+  d8_gather(va, XA + reg, t);
+  __builtin_amdgcn_sched_barrier(0);
+  d8_gather(vb, XB + reg, t);
+  dft_reg<8, S>(va);
+  interleave_ds_valu<8, NV / 2>();
+  d8_scatter0(va, XA + reg, t);
+  wave_fence();  // scatter before gather (other lanes' values)
+  d8_gather(va, XA + reg, t);
+  dft_reg<8, S>(vb);
+  interleave_ds_valu<16, NV / 2>();
+  d8_scatter0(vb, XB + reg, t);
+  wave_fence();
+  d8_gather(vb, XB + reg, t);
+  d8_pass1<S>(va, tw);
+  interleave_ds_valu<16, NV>();
+  d8_lane_exchange(va);
+  d8_pass2<S>(va, tw);
+  d8_pass1<S>(vb, tw);
+  d8_lane_exchange(vb);
+  d8_pass2<S>(vb, tw);
+}
+
+// Two forward paths (sub-transform order in, mode order out).
+template <int S, bool PRE, int NV, typename Real>
+__device__ __forceinline__ void d8_fwd2(cx<Real> (&va)[8], cx<Real> (&vb)[8], cx<Real> *XA,
+                                        cx<Real> *XB, const D8Tw<Real> &tw, int w, int l) {
+  if constexpr (PRE) __syncthreads();
+  const int c = 64 * w + l, t = l >> 1, reg = (2 * w + (l & 1)) * D8L<Real>::RL;
+  __builtin_amdgcn_sched_barrier(0);
+  dft_reg<8, S>(va);
+  __builtin_amdgcn_sched_barrier(0);
+  d8_scatter0(va, XA + reg, t);
+  wave_fence();
+  d8_gather(va, XA + reg, t);
+  dft_reg<8, S>(vb);
+  interleave_ds_valu<16, NV / 2>();
+  d8_scatter0(vb, XB + reg, t);
+  wave_fence();
+  d8_gather(vb, XB + reg, t);
+  d8_pass1<S>(va, tw);
+  interleave_ds_valu<16, NV>();
+  d8_lane_exchange(va);
+  d8_pass2<S>(va, tw);
+  // own regions: the sub-transform's gathers come before these writes
+  wave_fence();
+  d8_put(va, XA + reg, t);
+  d8_pass1<S>(vb, tw);
+  interleave_ds_valu<8, NV>();
+  d8_lane_exchange(vb);
+  d8_pass2<S>(vb, tw);
+  wave_fence();
+  d8_put(vb, XB + reg, t);
+  __syncthreads();
+  d8_cross_get(va, XA, c);
+  __builtin_amdgcn_sched_barrier(0);
+  d8_cross_get(vb, XB, c);
+  d8_cross_fwd<S>(va, tw);
+  interleave_ds_valu<8, NV>();
+  d8_cross_fwd<S>(vb, tw);
+}
+
+// LY: the two-level layout (0) or N = 2048 as 8 x 256 (1)
+template <typename Real, int N, int E, int PS, int LY = 0> struct DuoShape {
   using LP = LeanPlan<N, E>;
   static constexpr int W = LP::W;
   static constexpr int LB1 = LdsLen<LP::N1, PS>::value;
-  static constexpr int CTX = LP::WV * LB1;  // one transform's exchange context
+  static constexpr int CTX = LY == 1 ? D8L<Real>::CTX : LP::WV * LB1;  // one transform's exchange context
   static constexpr int LIMIT = 160 * 1024;
   static constexpr int NSET = 4 * CTX * (int)sizeof(cx<Real>) <= LIMIT ? 2 : 1;
   static constexpr int PER_INST = NSET * 2 * CTX;
@@ -457,13 +714,22 @@ template <typename Real, int N, int E, int PS> struct DuoShape {
   static constexpr int THREADS = 64 * W;
   static_assert(W > 1, "one instance spans several wavefronts");
   static_assert(LDS_BYTES <= LIMIT, "LDS over the gfx950 per-workgroup limit");
+  static_assert(LY == 0 || (N == D8::N && E == D8::E && PS == 3), "the 8 x 256 layout is N = 2048, E = 8");
 };
 
-// REC: record the stage inputs and inverse transforms for the adjoint
-template <typename Real, int N, int E, int PS, int NV, int FT, bool REC>
-__global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(RunArgs a) {
-  using SH = DuoShape<Real, N, E, PS>;
+// mode of slot m of thread (w, l)
+template <int LY, int N, int E> __device__ __forceinline__ int duo_mode(int w, int l, int m) {
+  if constexpr (LY == 1) return D8::mode(w, l, m);
+  else return WavePlan<N, E, 1, 0>::mode(w, l, m);
+}
+
+// REC: record the stage inputs and inverse transforms for the adjoint (two-
+// level layout only: the reverse sweeps read its slot order)
+template <typename Real, int N, int E, int PS, int NV, int FT, bool REC, int LY = 0>
+__global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_duo(RunArgs a) {
+  using SH = DuoShape<Real, N, E, PS, LY>;
   using WP = WavePlan<N, E, 1, 0>;
+  static_assert(!(REC && LY == 1), "no stage records in the 8 x 256 layout");
   constexpr bool ONESET = SH::NSET == 1;
   __shared__ cx<Real> lds[SH::PER_INST];
 
@@ -479,17 +745,21 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   const double *omg = a.omega + d.offset;
 
   std::conditional_t<
-      FT >= 2, FmaTw<N, E, Real, FT == 2>,
-      std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>>>
+      LY == 1, D8Tw<Real>,
+      std::conditional_t<FT >= 2, FmaTw<N, E, Real, FT == 2>,
+                         std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>>>>
       tw;
-  load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  if constexpr (LY == 1)
+    load_twiddle_source(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  else
+    load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> y[E], yw[E], va[E], vb[E];
   Real lr[E];
   double om[E];
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    const int i = WP::mode(w, lane, m);
+    const int i = duo_mode<LY, N, E>(w, lane, m);
     y[m] = A[i];
     lr[m] = (Real)(-0.5 * kap[i]);
     om[m] = omg[i];
@@ -545,7 +815,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       const cx<Real> w1 = lin(y[m], mi, s1);
       vb[m] = {y[m].re + hh * w1.re, y[m].im + hh * w1.im};
     });
-    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    if constexpr (LY == 1) d8_inv2<+1, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    else lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       rec_a(n, 0, mi, va[m]);
@@ -557,7 +828,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       vb[m] = cube(a2);
     });
     // ---- R1: K'_1, K'_2
-    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    if constexpr (LY == 1) d8_fwd2<-1, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    else lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> w1 = lin(y[m], mi, s1);
@@ -579,7 +851,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       vb[m] = yw[m];
     });
     // ---- R2: a_3 = IDFT(u_3), IDFT(y + h W_3)
-    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    if constexpr (LY == 1) d8_inv2<+1, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    else lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       rec_a(n, 2, mi, va[m]);
@@ -591,7 +864,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       vb[m] = cube(a4);
     });
     // ---- R3: K'_3, K'_4
-    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    if constexpr (LY == 1) d8_fwd2<-1, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    else lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       // i (g0/N) K'_3
@@ -607,7 +881,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
       cx<Real> *dst = ckpt + ckpt_slot * a.total + d.offset;
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
-        dst[WP::mode(w, lane, m)] = y[m];
+        dst[duo_mode<LY, N, E>(w, lane, m)] = y[m];
       });
       ++ckpt_slot;
     }
@@ -615,7 +889,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo(R
   bool bad = false;
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    A[WP::mode(w, lane, m)] = y[m];
+    A[duo_mode<LY, N, E>(w, lane, m)] = y[m];
     bad |= !(isfinite(y[m].re) && isfinite(y[m].im));
   });
   if (bad) atomicOr(&a.flags[id], 1);
@@ -832,6 +1106,16 @@ hipError_t launch_duo_adj(const AdjArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// the 8 x 256 layout: no stage records (its adjoint runs on a two-level variant)
+template <typename Real, int NV>
+hipError_t launch_duo8_fwd(const RunArgs &a, hipStream_t st) {
+  using SH = DuoShape<Real, D8::N, D8::E, 3, 1>;
+  if (a.stages) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((rk4_duo<Real, D8::N, D8::E, 3, NV, 2, false, 1>), dim3(a.count),
+                     dim3(SH::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+
 template <typename Real, int N, int E, int PS, int NV, int FT>
 hipError_t launch_duo_fwd(const RunArgs &a, hipStream_t st) {
   using SH = DuoShape<Real, N, E, PS>;
@@ -879,18 +1163,31 @@ template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant
                    &launch_duo_fwd<Real, N, E, PS, NV, FT>, nullptr};
 }
 
+// 8 x 256 layout: reported with two sub-transforms per wave (v = 2)
+template <typename Real, int NV> constexpr Variant duo8_variant() {
+  using SH = DuoShape<Real, D8::N, D8::E, 3, 1>;
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, D8::N, D8::E, 2, 3, NV + 32, 2, 1,
+                 SH::THREADS, SH::LDS_BYTES, &launch_duo8_fwd<Real, NV>, nullptr};
+}
+
 // The first entry of a size is its default.  N = 512 and 1024 run four
 // elements per thread (two and four wavefronts per instance: 39% and 21%
 // faster than the previous defaults at 256 instances); N = 4096 runs eight
 // wavefronts per instance, two per SIMD, with the twiddles rebuilt on use
 // (the register-held tables do not fit), 5% faster than the lean kernel.
-// N = 2048 uses the multiply-add form (FT = 2): 2747 VALU instructions per
-// wave and step in place of 2967, 466.6 against 474.9 ms for 5e4 steps of
-// 256 instances (FP32 7.42 against 7.94 us per step); at N = 1024 (radix-4
-// passes) it saves 7% of the instructions and no time, so it is not built.
+// N = 2048: the 8 x 256 layout with the multiply-add butterflies (FP64),
+// else the two-level layout with them (FT = 2).  Round-robin timings of
+// 256 x N=2048 (sweep workload, us per step): 8 x 256 NV = 5 / 6 / 7 / 8:
+// 9.12 / 9.08 / 9.04 / 9.04; two-level FT = 2 NV = 5: 9.38 (2747 VALU
+// instructions per wave and step in place of 2967 with every power held:
+// 9.55); FP32 8 x 256 7.07, two-level FT = 2 7.08 (7.52 with every power
+// held).  At N = 1024 (radix-4 passes) the multiply-add form saves 7% of the
+// instructions and no time, so it is not built there.  The 8 x 256 layout
+// records no stage inputs: its adjoint runs on the two-level variant.
 static const Variant kDuoVariants[] = {
     duo_variant<double, 512, 4, 2, 4, 1>(),  duo_variant<double, 1024, 4, 2, 5, 1>(),
     duo_variant<double, 1024, 4, 2, 4, 1>(), duo_variant<double, 1024, 8, 3, 4, 1>(),
+    duo8_variant<double, 7>(),               duo8_variant<double, 5>(),
     duo_variant<double, 2048, 8, 3, 5, 2>(), duo_variant<double, 2048, 8, 3, 4, 2>(),
     duo_variant<double, 2048, 8, 3, 5, 1>(), duo_variant<double, 2048, 8, 3, 4, 1>(),
     duo_variant<double, 2048, 8, 3, 4, 0>(), duo_variant<double, 4096, 8, 3, 4, 0>(),
@@ -905,6 +1202,7 @@ static const Variant kDuoVariantsF32[] = {
     duo_variant<float, 512, 4, 2, 4, 1>(),  duo_variant<float, 1024, 4, 2, 5, 1>(),
     duo_variant<float, 1024, 4, 2, 4, 1>(), duo_variant<float, 1024, 8, 3, 5, 1>(),
     duo_variant<float, 2048, 8, 3, 5, 2>(), duo_variant<float, 2048, 8, 3, 4, 2>(),
+    duo8_variant<float, 5>(),
     duo_variant<float, 2048, 8, 3, 5, 1>(), duo_variant<float, 2048, 8, 3, 4, 1>(),
 };
 
