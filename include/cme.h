@@ -245,7 +245,9 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * transform per team of threads, ordered by workgroup barriers, or at
  * wavefront scope when the workgroup is one wavefront, 1: two-level
  * transform with one workgroup barrier per transform, 2: two-level
- * transforms in four rounds of two interleaved transforms per RK4 step,
+ * transforms in four rounds of two interleaved transforms per RK4 step
+ * (V = 2: N = 2048 as an 8-point step over each thread's modes and two
+ * 256-point sub-transforms per wavefront),
  * 3: two-level transform with twiddles rebuilt on use, sized for two
  * wavefronts per SIMD, 4: split-step map, 5: RK4 with the padded sum on
  * N-point transforms for instances of N/2 modes, 6: four-step transforms
@@ -264,7 +266,8 @@ int cme_list_kernels(int32_t precision, int32_t n_modes, int32_t *ids, int32_t c
  * workgroup size, LDS bytes, and a kind-specific tuning field (kind 1:
  * sub-transform exchange, 0 all through LDS, 1 high lane bits in registers;
  * kind 2: VALU instructions scheduled per LDS instruction, + 16 when all
- * twiddles are held in registers; kinds 6, 8, 9, 10: wavefronts per
+ * twiddles are held in registers, + 32 when the twiddled butterflies are
+ * fused multiply-adds; kinds 6, 8, 9, 10: wavefronts per
  * workgroup; kind 13: operand prefetch distance of the stage arithmetic, + 16
  * when the sub-transform twiddles are formed from one base per pass, + 32 with
  * the state and + 64 with omega' held in registers; kind 14: the prefetch

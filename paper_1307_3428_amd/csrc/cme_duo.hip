@@ -251,13 +251,71 @@ __device__ __forceinline__ void cross_twiddles(cx<Real> (&t)[Q][WV],
   }); });
 }
 
+// v_permlane32_swap: the upper 32 lanes of a trade places with the lower 32
+// lanes of b; v_permlane16_swap: the odd rows (16 lanes) of a with the even
+// rows of b
+__device__ __forceinline__ void lane_swap32(double &a, double &b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+__device__ __forceinline__ void lane_swap16(double &a, double &b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+__device__ __forceinline__ void lane_swap32(float &a, float &b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+__device__ __forceinline__ void lane_swap16(float &a, float &b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// The last exchange of a 256-point sub-transform at four modes per thread
+// (radix-4 passes, 64 lanes): after the third pass element r of lane t
+// belongs at position 64 (t >> 4) + 16 r + (t & 15), and the last pass needs
+// position t' + 64 m in slot m, so register bits 0-1 trade places with lane
+// bits 4-5 and nothing else moves: two swap stages, no renaming.
+// sizes whose last sub-transform exchange lane_exchange4 does
+template <int N, int E> constexpr bool lx_ok() {
+  using PL = typename LeanPlan<N, E>::Sub;
+  return E == 4 && PL::P >= 2 && PL::radix(PL::P - 2) == 4 && PL::ns(PL::P - 2) == 16;
+}
+template <int E, typename Real> __device__ __forceinline__ void lane_exchange4(cx<Real> (&v)[E]) {
+  static_assert(E == 4, "four modes per thread");
+  sfor<0, 2>([&](auto ri) {
+    constexpr int r = decltype(ri)::value;  // 0 1
+    lane_swap32(v[r].re, v[r + 2].re);
+    lane_swap32(v[r].im, v[r + 2].im);
+  });
+  sfor<0, 2>([&](auto ri) {
+    constexpr int r = 2 * decltype(ri)::value;  // 0 2
+    lane_swap16(v[r].re, v[r + 1].re);
+    lane_swap16(v[r].im, v[r + 1].im);
+  });
+}
+
 // The passes of two independent wave-local transforms of sign S, a in region
 // ra and b in region rb, software-pipelined.  On entry a has had its first
 // pass's butterflies (lean_compute<0>) and b holds its input; on exit a is
 // transformed and b still needs its last pass's butterflies.  In between, a's
 // scatter and next gather interleave with b's butterflies of the same pass,
 // and b's with a's butterflies of the next pass.
-template <int N, int E, int S, int PS, int NV, typename Real, typename TW>
+// LX: the last exchange in registers (lane_exchange4; 256-point
+// sub-transforms at four modes per thread, see lx_ok)
+template <int N, int E, int S, int PS, int NV, bool LX = false, typename Real, typename TW>
 __device__ __forceinline__ void pair_passes(cx<Real> (&va)[E], cx<Real> (&vb)[E], cx<Real> *ra,
                                             cx<Real> *rb, const TW &tw, int l) {
   using LP = LeanPlan<N, E>;
@@ -268,18 +326,27 @@ __device__ __forceinline__ void pair_passes(cx<Real> (&va)[E], cx<Real> (&vb)[E]
     constexpr int R = PL::radix(p), R1 = PL::radix(p + 1);
     cx<Real> t[R], t1[R1];
     if constexpr (PL::ns(p) > 1) pass_twiddles<p>(t, tw);
-    lean_scatter<N, E, PS, p>(va, ra, l);
-    wave_fence();  // scatter before gather (other lanes' values)
-    lean_gather<PS>(va, ra, l);
-    lean_compute<N, E, S, p, FMA>(vb, t);
-    // a pass without twiddles has about half the VALU work
-    interleave_ds_valu<2 * E, (PL::ns(p) > 1 ? NV : NV / 2)>();
-    pass_twiddles<p + 1>(t1, tw);
-    lean_scatter<N, E, PS, p>(vb, rb, l);
-    wave_fence();
-    lean_gather<PS>(vb, rb, l);
-    lean_compute<N, E, S, p + 1, FMA>(va, t1);
-    interleave_ds_valu<2 * E, NV>();
+    if constexpr (LX && p == PL::P - 2) {
+      static_assert(E == 4 && R == 4 && PL::ns(p) == 16, "lane exchange: 256-point, radix 4");
+      lane_exchange4(va);
+      lean_compute<N, E, S, p, FMA>(vb, t);
+      pass_twiddles<p + 1>(t1, tw);
+      lane_exchange4(vb);
+      lean_compute<N, E, S, p + 1, FMA>(va, t1);
+    } else {
+      lean_scatter<N, E, PS, p>(va, ra, l);
+      wave_fence();  // scatter before gather (other lanes' values)
+      lean_gather<PS>(va, ra, l);
+      lean_compute<N, E, S, p, FMA>(vb, t);
+      // a pass without twiddles has about half the VALU work
+      interleave_ds_valu<2 * E, (PL::ns(p) > 1 ? NV : NV / 2)>();
+      pass_twiddles<p + 1>(t1, tw);
+      lean_scatter<N, E, PS, p>(vb, rb, l);
+      wave_fence();
+      lean_gather<PS>(vb, rb, l);
+      lean_compute<N, E, S, p + 1, FMA>(va, t1);
+      interleave_ds_valu<2 * E, NV>();
+    }
   });
 }
 
@@ -375,7 +442,8 @@ __device__ __forceinline__ void lean_cross_idft(
 // Two forward paths (mode order in, scrambled order out) in contexts XA, XB,
 // every LDS exchange of one sequence interleaved with arithmetic of the other.
 // PRE: barrier first (single buffer set).
-template <int N, int E, int S, int PS, bool PRE, int NV, typename Real, typename TW>
+template <int N, int E, int S, int PS, bool PRE, int NV, bool LX = false, typename Real,
+          typename TW>
 __device__ __forceinline__ void lean_fwd2(cx<Real> (&va)[E], cx<Real> (&vb)[E], cx<Real> *XA,
                                           cx<Real> *XB, const TW &tw, int w, int l) {
   using LP = LeanPlan<N, E>;
@@ -401,12 +469,13 @@ __device__ __forceinline__ void lean_fwd2(cx<Real> (&va)[E], cx<Real> (&vb)[E], 
   lean_gather<PS>(vb, XB + r0, l);
   lean_compute<N, E, S, 0>(va, (const cx<Real> *)nullptr);
   interleave_ds_valu<E, NV / 2>();
-  pair_passes<N, E, S, PS, NV>(va, vb, XA + r0, XB + r0, tw, l);
+  pair_passes<N, E, S, PS, NV, LX>(va, vb, XA + r0, XB + r0, tw, l);
   lean_compute_last<N, E, S>(vb, tw);
 }
 
 // Two back paths (scrambled order in, mode order out) in contexts XA, XB.
-template <int N, int E, int S, int PS, bool PRE, int NV, typename Real, typename TW>
+template <int N, int E, int S, int PS, bool PRE, int NV, bool LX = false, typename Real,
+          typename TW>
 __device__ __forceinline__ void lean_back2(cx<Real> (&va)[E], cx<Real> (&vb)[E], cx<Real> *XA,
                                            cx<Real> *XB, const TW &tw, int w, int l) {
   using LP = LeanPlan<N, E>;
@@ -417,7 +486,7 @@ __device__ __forceinline__ void lean_back2(cx<Real> (&va)[E], cx<Real> (&vb)[E],
   __builtin_amdgcn_sched_barrier(0);
   lean_compute<N, E, S, 0>(va, (const cx<Real> *)nullptr);
   __builtin_amdgcn_sched_barrier(0);
-  pair_passes<N, E, S, PS, NV>(va, vb, XA + r0, XB + r0, tw, l);
+  pair_passes<N, E, S, PS, NV, LX>(va, vb, XA + r0, XB + r0, tw, l);
   // own regions: the transform's last gathers come before these scatters
   wave_fence();
   const int g0 = r0 + lpad<PS>(l);
@@ -507,38 +576,6 @@ template <typename Real>
 __device__ __forceinline__ void load_twiddle_source(D8Tw<Real> &tw, const cx<Real> *tab, int w,
                                                     int l) {
   load_d8_twiddles(tw, tab, w, l);
-}
-
-// v_permlane32_swap: the upper 32 lanes of a trade places with the lower 32
-// lanes of b; v_permlane16_swap: the odd rows (16 lanes) of a with the even
-// rows of b
-__device__ __forceinline__ void lane_swap32(double &a, double &b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
-  const auto hi =
-      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
-  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
-  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
-}
-__device__ __forceinline__ void lane_swap16(double &a, double &b) {
-  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
-  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)ua, (unsigned)ub, false, false);
-  const auto hi =
-      __builtin_amdgcn_permlane16_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
-  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
-  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
-}
-__device__ __forceinline__ void lane_swap32(float &a, float &b) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
-                                                  __builtin_bit_cast(unsigned, b), false, false);
-  a = __builtin_bit_cast(float, (unsigned)r[0]);
-  b = __builtin_bit_cast(float, (unsigned)r[1]);
-}
-__device__ __forceinline__ void lane_swap16(float &a, float &b) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, a),
-                                                  __builtin_bit_cast(unsigned, b), false, false);
-  a = __builtin_bit_cast(float, (unsigned)r[0]);
-  b = __builtin_bit_cast(float, (unsigned)r[1]);
 }
 
 // The second exchange of a sub-transform.  After pass 1 element r of thread
@@ -701,7 +738,10 @@ __device__ __forceinline__ void d8_fwd2(cx<Real> (&va)[8], cx<Real> (&vb)[8], cx
   d8_cross_fwd<S>(vb, tw);
 }
 
-// LY: the two-level layout (0) or N = 2048 as 8 x 256 (1)
+// LY: the two-level layout (0), N = 2048 as 8 x 256 (1), or the two-level
+// layout with the last sub-transform exchange in registers (2, four modes per
+// thread; the slot order is that of 0, so stage records and the reverse
+// sweep are shared)
 template <typename Real, int N, int E, int PS, int LY = 0> struct DuoShape {
   using LP = LeanPlan<N, E>;
   static constexpr int W = LP::W;
@@ -714,7 +754,7 @@ template <typename Real, int N, int E, int PS, int LY = 0> struct DuoShape {
   static constexpr int THREADS = 64 * W;
   static_assert(W > 1, "one instance spans several wavefronts");
   static_assert(LDS_BYTES <= LIMIT, "LDS over the gfx950 per-workgroup limit");
-  static_assert(LY == 0 || (N == D8::N && E == D8::E && PS == 3), "the 8 x 256 layout is N = 2048, E = 8");
+  static_assert(LY != 1 || (N == D8::N && E == D8::E && PS == 3), "the 8 x 256 layout is N = 2048, E = 8");
 };
 
 // mode of slot m of thread (w, l)
@@ -816,7 +856,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_d
       vb[m] = {y[m].re + hh * w1.re, y[m].im + hh * w1.im};
     });
     if constexpr (LY == 1) d8_inv2<+1, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
-    else lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    else lean_fwd2<N, E, +1, PS, ONESET, NV, LY == 2>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       rec_a(n, 0, mi, va[m]);
@@ -829,7 +869,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_d
     });
     // ---- R1: K'_1, K'_2
     if constexpr (LY == 1) d8_fwd2<-1, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
-    else lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    else lean_back2<N, E, -1, PS, ONESET, NV, LY == 2>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> w1 = lin(y[m], mi, s1);
@@ -852,7 +892,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_d
     });
     // ---- R2: a_3 = IDFT(u_3), IDFT(y + h W_3)
     if constexpr (LY == 1) d8_inv2<+1, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
-    else lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    else lean_fwd2<N, E, +1, PS, ONESET, NV, LY == 2>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       rec_a(n, 2, mi, va[m]);
@@ -865,7 +905,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_d
     });
     // ---- R3: K'_3, K'_4
     if constexpr (LY == 1) d8_fwd2<-1, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
-    else lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    else lean_back2<N, E, -1, PS, ONESET, NV, LY == 2>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       // i (g0/N) K'_3
@@ -1002,7 +1042,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       va[m] = yb1[m];
       vb[m] = clin(cx<Real>{hw1 * yb1[m].re, hw1 * yb1[m].im}, mi, s4);
     });
-    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    lean_fwd2<N, E, +1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> q4 = kerr_t(mig(cx<Real>{hw1 * va[m].re, hw1 * va[m].im}), ra[m]);
@@ -1012,7 +1052,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       vb[m] = kerr_t(mig(x3), rb[m]);
     });
     // ---- B: DFT(q_4), DFT(q_3)
-    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    lean_back2<N, E, -1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> k4 = {hw1 * yb1[m].re, hw1 * yb1[m].im};
@@ -1033,7 +1073,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     //         IDFT(h/6 ybar' + h/2 conj(L_2) kbar_2) = h/6 Ybar + h/2 P_2
     load_a(ra, nn, 1);
     load_a(rb, nn, 0);
-    lean_fwd2<N, E, +1, PS, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    lean_fwd2<N, E, +1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> q2 = kerr_t(mig(va[m]), ra[m]);
@@ -1042,7 +1082,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       vb[m] = kerr_t(mig(x1), rb[m]);
     });
     // ---- D: DFT(q_2), DFT(q_1)
-    lean_back2<N, E, -1, PS, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    lean_back2<N, E, -1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> c2 = clin(k2[m], mi, s2);
@@ -1116,15 +1156,15 @@ hipError_t launch_duo8_fwd(const RunArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename Real, int N, int E, int PS, int NV, int FT>
+template <typename Real, int N, int E, int PS, int NV, int FT, int LY = 0>
 hipError_t launch_duo_fwd(const RunArgs &a, hipStream_t st) {
-  using SH = DuoShape<Real, N, E, PS>;
+  using SH = DuoShape<Real, N, E, PS, LY>;
   if (a.stages)
-    hipLaunchKernelGGL((rk4_duo<Real, N, E, PS, NV, FT, true>), dim3(a.count), dim3(SH::THREADS),
-                       0, st, a);
+    hipLaunchKernelGGL((rk4_duo<Real, N, E, PS, NV, FT, true, LY>), dim3(a.count),
+                       dim3(SH::THREADS), 0, st, a);
   else
-    hipLaunchKernelGGL((rk4_duo<Real, N, E, PS, NV, FT, false>), dim3(a.count), dim3(SH::THREADS),
-                       0, st, a);
+    hipLaunchKernelGGL((rk4_duo<Real, N, E, PS, NV, FT, false, LY>), dim3(a.count),
+                       dim3(SH::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1152,15 +1192,19 @@ template <typename Real, int N, int E, int PS, int NV, int FT> constexpr AdjLaun
   else return &launch_duo_adj<Real, N, E, PS, NV, FT == 2 ? 3 : 1>;
 }
 
-template <typename Real, int N, int E, int PS, int NV, int FT> constexpr Variant duo_variant() {
-  using SH = DuoShape<Real, N, E, PS>;
+// LX: the last sub-transform exchange in registers (layout 2), reported as
+// + 64 in the tuning field
+template <typename Real, int N, int E, int PS, int NV, int FT, bool LX = false>
+constexpr Variant duo_variant() {
+  constexpr int LY = LX ? 2 : 0;
+  using SH = DuoShape<Real, N, E, PS, LY>;
   if constexpr (std::is_same<Real, double>::value)
-    return Variant{0, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
-                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, duo_adj_ptr<Real, N, E, PS, NV, FT>(), 0,
+    return Variant{0, N, E, 1, PS, NV + 16 * FT + 64 * LX, 2, 1, SH::THREADS, SH::LDS_BYTES,
+                   &launch_duo_fwd<Real, N, E, PS, NV, FT, LY>, duo_adj_ptr<Real, N, E, PS, NV, FT>(), 0,
                    N / (64 * E) < 8 ? 1 : 0};
   else  // FP32 plans have no adjoint
-    return Variant{1, N, E, 1, PS, NV + 16 * FT, 2, 1, SH::THREADS, SH::LDS_BYTES,
-                   &launch_duo_fwd<Real, N, E, PS, NV, FT>, nullptr};
+    return Variant{1, N, E, 1, PS, NV + 16 * FT + 64 * LX, 2, 1, SH::THREADS, SH::LDS_BYTES,
+                   &launch_duo_fwd<Real, N, E, PS, NV, FT, LY>, nullptr};
 }
 
 // 8 x 256 layout: reported with two sub-transforms per wave (v = 2)
@@ -1184,7 +1228,11 @@ template <typename Real, int NV> constexpr Variant duo8_variant() {
 // held).  At N = 1024 (radix-4 passes) the multiply-add form saves 7% of the
 // instructions and no time, so it is not built there.  The 8 x 256 layout
 // records no stage inputs: its adjoint runs on the two-level variant.
+// N = 512 and 1024 take the last sub-transform exchange in registers
+// (lane_exchange4): 256 x N=1024 6.78 -> 6.07 us per step (FP32 4.56 ->
+// 4.29), 256 x N=512 4.93 -> 4.86 (FP32 3.91 -> 3.81).
 static const Variant kDuoVariants[] = {
+    duo_variant<double, 512, 4, 2, 4, 1, true>(), duo_variant<double, 1024, 4, 2, 5, 1, true>(),
     duo_variant<double, 512, 4, 2, 4, 1>(),  duo_variant<double, 1024, 4, 2, 5, 1>(),
     duo_variant<double, 1024, 4, 2, 4, 1>(), duo_variant<double, 1024, 8, 3, 4, 1>(),
     duo8_variant<double, 7>(),               duo8_variant<double, 5>(),
@@ -1199,6 +1247,7 @@ static const Variant kDuoVariants[] = {
 // N = 512, 1024 (four modes per thread) and 2048: 36%, 38% and 17% faster
 // than the one-transform wave kernel at 256 instances.
 static const Variant kDuoVariantsF32[] = {
+    duo_variant<float, 512, 4, 2, 4, 1, true>(), duo_variant<float, 1024, 4, 2, 5, 1, true>(),
     duo_variant<float, 512, 4, 2, 4, 1>(),  duo_variant<float, 1024, 4, 2, 5, 1>(),
     duo_variant<float, 1024, 4, 2, 4, 1>(), duo_variant<float, 1024, 8, 3, 5, 1>(),
     duo_variant<float, 2048, 8, 3, 5, 2>(), duo_variant<float, 2048, 8, 3, 4, 2>(),
