@@ -182,24 +182,22 @@ const Variant *default_variant(int precision, int n, int integrator) {
 }
 
 // Classic RK4 (cyclic sum) at N = 8192, by measured crossover (us per step
-// for the whole class, per-mode kappa; kappa the same for every mode in
-// brackets):
+// for the whole class, per-mode kappa):
 //   FP64: the staged kernels spread each instance over many CUs and win
-//   for small classes (four-wave workgroups: 39.7 at 1 instance, 50.8 at
-//   24, 54.7 at 32, 61.6 at 40, 69.5 at 64); rk4_stream, one instance per
-//   CU with the state in global memory, from 32 on (55.4 (52.1) at 1,
-//   55.8 (52.5) at 24, 56.0 (52.4) at 32, 55.7 (52.3) at 40, 58.4 (55.6)
-//   at 64);
-//   FP32: rk4_stream at every size (38.5 (34.9) at 1 to 38.6 (35.2) at 64,
-//   against 38.3 ... 38.8 for the one-transform wave kernel, which spills).
+//   for small classes (four-wave workgroups: 42.7 at 1 instance, 45.6 at 8,
+//   49.1 at 16, 53.1 at 24, 57.1 at 32); rk4_stream in the 16 x 512 layout,
+//   one instance per CU with the state in global memory, from 12 on (47.2
+//   at 1, 47.1 at 8 to 32, 54.0 at 128);
+//   FP32: rk4_stream at every size (27.3 at 1 to 27.4 at 128, against
+//   38.3 ... 38.8 for the one-transform wave kernel, which spills).
 // RK4IP at N = 8192:
-//   FP64: rk4ip_stream at every size (49.9 at 1, 53.2 at 64, 56.6 at 128
-//   instances, against 58.5, 78.9 and 96.8 for the staged kernels and 96 to
+//   FP64: rk4ip_stream at every size (44.3 at 1, 48.6 at 64, 52.6 at 128
+//   instances, against 58.4, 77.9 and 96.5 for the staged kernels and 96 to
 //   126 for the one-transform wave kernel);
-//   FP32: the wave kernel, its state in registers, for small classes (30.8
-//   at 16, 31.2 at 64, 35.0 at 100, 36.3 at 112), rk4ip_stream from 112 on
-//   (35.9 at 16, 36.5 at 100, 36.5 at 112, 36.4 at 128, against 39.6 for
-//   the wave kernel, whose spill traffic grows with the class).
+//   FP32: the wave kernel, its state in registers, for small classes (30.9
+//   at 16, 31.2 at 64, 35.0 at 100), rk4ip_stream from 80 on (32.0 at 16,
+//   32.2 at 64, 32.9 at 100, 33.2 at 128, against 39.0 for the wave
+//   kernel, whose spill traffic grows with the class).
 const Variant *class_default(int precision, int n, int integrator, size_t count) {
   const Variant *v = default_variant(precision, n, integrator);
   if (n != 8192 || (integrator != CME_RK4 && integrator != CME_RK4IP)) return v;
@@ -214,8 +212,8 @@ const Variant *class_default(int precision, int n, int integrator, size_t count)
   };
   const Variant *pick = nullptr;
   if (integrator == CME_RK4IP)
-    pick = precision == CME_F32 && count < 112 ? find(7, 0) : find(14, 0);
-  else if (precision == CME_F64) pick = count < 32 ? find(6, 256) : find(13, 0);
+    pick = precision == CME_F32 && count < 80 ? find(7, 0) : find(14, 0);
+  else if (precision == CME_F64) pick = count < 12 ? find(6, 256) : find(13, 0);
   else pick = find(13, 0);
   return pick ? pick : v;
 }

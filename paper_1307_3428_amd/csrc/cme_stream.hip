@@ -208,6 +208,164 @@ __device__ __forceinline__ void stream_backpath(cx<Real> (&v)[E], cx<Real> *X, c
   sfor<0, WV>([&](auto ri) { v[decltype(ri)::value] = z[decltype(ri)::value]; });
 }
 
+// N = 8192 as 16 x 512 on alternate lanes (IL).  Thread c = 64 w + l holds
+// modes c + 512 m, as in the two-level layout, so the stage arithmetic is
+// unchanged.  The inverse path takes the 16-point DFT over the thread's
+// slots, twiddles w^(c k1), and writes region k1 at position c; after the
+// barrier wave w runs the 512-point sub-transforms of regions 2 w and
+// 2 w + 1 on alternate lanes (lane = 2 t + s), thread t holding positions
+// t + 32 m of one of them: radix 16, one exchange through its region, radix
+// 16, then an exchange that only trades register bit 0 for t bit 4 (lane
+// bit 5: one v_permlane32_swap stage and a renaming of slots), radix 2.
+// Against the two-level layout (two 512-point sub-transforms per wave at
+// eight modes per thread, two exchanges through LDS each) a transform makes
+// one LDS exchange fewer.  The forward path is the mirror image.
+template <typename Real> struct S16 {
+  static constexpr int N = 8192, E = 16;
+  // region length: 512 positions with one pad element every 16 (544), plus
+  // an offset that starts the regions of alternate lanes 64 bytes apart
+  // modulo 128 (regions 128 bytes apart share the LDS banks)
+  static constexpr int RL = 544 + (sizeof(Real) == 8 ? 4 : 8);
+};
+
+// w^c for the cross twiddles (powers formed on use), the pass-1 base
+// exp(-2 pi i (t mod 16) / 256) and the pass-2 base exp(-2 pi i t / 512)
+template <typename Real> struct S16Tw {
+  cx<Real> bx, b1, b2;
+};
+template <typename Real>
+__device__ __forceinline__ void load_s16_twiddles(S16Tw<Real> &tw, const cx<Real> *__restrict__ tab,
+                                                  int w, int l) {
+  const int t = l >> 1;
+  tw.bx = tab[l + 64 * w];
+  tw.b1 = tab[32 * (t & 15)];
+  tw.b2 = tab[16 * t];
+}
+
+template <typename Real>
+__device__ __forceinline__ void s16_swap32(double &a, double &b) {
+  const uint64_t ua = __builtin_bit_cast(uint64_t, a), ub = __builtin_bit_cast(uint64_t, b);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)ua, (unsigned)ub, false, false);
+  const auto hi =
+      __builtin_amdgcn_permlane32_swap((unsigned)(ua >> 32), (unsigned)(ub >> 32), false, false);
+  a = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+  b = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+template <typename Real>
+__device__ __forceinline__ void s16_swap32(float &a, float &b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a),
+                                                  __builtin_bit_cast(unsigned, b), false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// One 512-point sub-transform of sign S in place in v (slot m: position
+// t + 32 m, natural order in and out), its one LDS exchange through the
+// region R.
+template <int S, typename Real>
+__device__ __forceinline__ void s16_sub(cx<Real> (&v)[16], cx<Real> *R, const S16Tw<Real> &tw,
+                                        int t) {
+  // pass 0: element r goes to position 16 t + r
+  dft_reg<16, S>(v);
+  wave_sync();  // the region's earlier reads come before these writes
+  const int b = lpad<4>(16 * t);
+  sfor<0, 16>([&](auto ri) { R[b + decltype(ri)::value] = v[decltype(ri)::value]; });
+  wave_sync();
+  sfor<0, 16>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    v[m] = R[lpad<4>(t + 32 * m)];
+  });
+  // pass 1 (NS = 16): element r goes to position 256 (t >> 4) + 16 r + (t & 15)
+  {
+    cx<Real> tp[16];
+    pow_fill<16>(tp, tw.b1);
+    sfor<1, 16>([&](auto ri) {
+      constexpr int r = decltype(ri)::value;
+      v[r] = ctw<S>(v[r], tp[r]);
+    });
+  }
+  dft_reg<16, S>(v);
+  // pass 2 needs position t' + 32 m in slot m: the source thread agrees with
+  // t' in bits 0-3 and has bit 4 = m >> 3; the element is r = 2 (m & 7) +
+  // (t' >> 4).  Swapping the odd registers of the lower half-wave with the
+  // even ones of the upper half trades register bit 0 for t bit 4; slot m is
+  // then register 2 (m & 7) + (m >> 3).
+  sfor<0, 8>([&](auto ki) {
+    constexpr int k = 2 * decltype(ki)::value;
+    s16_swap32<Real>(v[k].re, v[k + 1].re);
+    s16_swap32<Real>(v[k].im, v[k + 1].im);
+  });
+  {
+    cx<Real> u[16];
+    sfor<0, 16>([&](auto mi) {
+      constexpr int m = decltype(mi)::value;
+      u[m] = v[2 * (m & 7) + (m >> 3)];
+    });
+    sfor<0, 16>([&](auto mi) { v[decltype(mi)::value] = u[decltype(mi)::value]; });
+  }
+  // pass 2 (NS = 256): butterfly q on slots q and q + 8, twiddle
+  // exp(-2 pi i (t + 32 q) / 512) = b2 exp(-2 pi i q / 16)
+  sfor<0, 8>([&](auto qi) {
+    constexpr int q = decltype(qi)::value;
+    cx<Real> x = ctw<S>(v[q + 8], tw.b2);
+    if constexpr (q > 0) x = twc<S, q, 16>(x);
+    const cx<Real> a = v[q];
+    v[q] = cadd(a, x);
+    v[q + 8] = csub(a, x);
+  });
+}
+
+// Inverse path (mode order in, sub-transform order out).  PRE: barrier first
+// (one exchange buffer: the previous forward path's gathers).
+template <int S, bool PRE, typename Real>
+__device__ __forceinline__ void s16_inv(cx<Real> (&v)[16], cx<Real> *X, const S16Tw<Real> &tw,
+                                        int w, int l) {
+  constexpr int RL = S16<Real>::RL;
+  if constexpr (PRE) cross_sync<8>();
+  dft_reg<16, S>(v);
+  {
+    cx<Real> tp[16];
+    pow_fill<16>(tp, tw.bx);
+    const int o = lpad<4>(l + 64 * w);
+    sfor<0, 16>([&](auto ki) {
+      constexpr int k1 = decltype(ki)::value;
+      X[k1 * RL + o] = k1 == 0 ? v[0] : ctw<S>(v[k1], tp[k1]);
+    });
+  }
+  cross_sync<8>();
+  const int t = l >> 1;
+  cx<Real> *R = X + (2 * w + (l & 1)) * RL;
+  sfor<0, 16>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    v[m] = R[lpad<4>(t + 32 * m)];
+  });
+  s16_sub<S>(v, R, tw, t);
+}
+
+// Forward path (sub-transform order in, mode order out); the sub-transform
+// runs in X (own region), the exchange goes through Y.
+template <int S, typename Real>
+__device__ __forceinline__ void s16_fwd(cx<Real> (&v)[16], cx<Real> *X, cx<Real> *Y,
+                                        const S16Tw<Real> &tw, int w, int l) {
+  constexpr int RL = S16<Real>::RL;
+  const int t = l >> 1, reg = (2 * w + (l & 1)) * RL;
+  s16_sub<S>(v, X + reg, tw, t);
+  if (Y == X) wave_sync();  // own region: the sub-transform's last reads come first
+  sfor<0, 16>([&](auto mi) {
+    constexpr int m = decltype(mi)::value;
+    Y[reg + lpad<4>(t + 32 * m)] = v[m];
+  });
+  cross_sync<8>();
+  cx<Real> tp[16];
+  pow_fill<16>(tp, tw.bx);
+  const int o = lpad<4>(l + 64 * w);
+  sfor<0, 16>([&](auto ki) {
+    constexpr int k1 = decltype(ki)::value;
+    v[k1] = k1 == 0 ? Y[o] : ctw<S>(Y[k1 * RL + o], tp[k1]);
+  });
+  dft_reg<16, S>(v);
+}
+
 // Raw buffer accesses: one 32-bit per-lane offset register plus a constant
 // per-slot offset in a scalar register, so that the addresses of the E slots
 // a thread owns cost no 64-bit registers (hoisted out of the time loop, 64-bit
@@ -241,7 +399,9 @@ __device__ __forceinline__ void buf_store(T x, __amdgpu_buffer_rsrc_t r, int vo,
 // stage; it is written back after the last step.  OR: omega' held in
 // registers for the launch (16 values per thread) instead of read at every
 // stage, and in FP32 -kappa/2 as well.
-template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR>
+// IL: the 16 x 512 layout on alternate lanes (S16)
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR,
+          bool IL = false>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4_stream(RunArgs a) {
   constexpr int TP = 0;
@@ -249,6 +409,9 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   using SH = WaveShape<Real, N, E, V, PS, TP>;
   using WP = WavePlan<N, E, V, TP>;
   static_assert(WP::W > 1 && SH::IPB == 1, "one instance per workgroup");
+  static_assert(!IL || (N == S16<Real>::N && E == S16<Real>::E && V == 2 && WP::W == 8),
+                "the 16 x 512 layout is N = 8192 at 16 modes per thread");
+  static_assert(!IL || 16 * S16<Real>::RL <= SH::WV * SH::LB1, "16 x 512 regions in one buffer");
   __shared__ cx<Real> lds[SH::PER_INST];
 
   const int lane = (int)threadIdx.x & 63;
@@ -270,8 +433,11 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   static_assert(WP::Q == 1, "one cross-wave element per slot");
   const int i0 = lane + 64 * w;
 
-  StreamTw<N, E, V, PB, Real> tw;
-  load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  std::conditional_t<IL, S16Tw<Real>, StreamTw<N, E, V, PB, Real>> tw;
+  if constexpr (IL)
+    load_s16_twiddles(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  else
+    load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> v[E];
   cx<Real> yr[YR ? E : 1];
@@ -309,13 +475,15 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
         // arithmetic reads it back from the state, k_1 or U)
           const double sig = sigma_at(d.sigma0, d.sigma1, d.tau_ramp, t0 + kCw[s] * h);
         // with one buffer the forward path fences the previous back path's reads
-        stream_fwdpath<N, E, V, +1, PS, !SH::TWO, PB>(v, X, tw, w, lane);
+        if constexpr (IL) s16_inv<+1, !SH::TWO>(v, X, tw, w, lane);
+        else stream_fwdpath<N, E, V, +1, PS, !SH::TWO, PB>(v, X, tw, w, lane);
         sfor<0, E>([&](auto mi) {
           constexpr int m = decltype(mi)::value;
           const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
           v[m] = {p * v[m].re, p * v[m].im};
         });
-        stream_backpath<N, E, V, -1, PS, PB>(v, X, Y, tw, w, lane);
+        if constexpr (IL) s16_fwd<-1>(v, X, Y, tw, w, lane);
+        else stream_backpath<N, E, V, -1, PS, PB>(v, X, Y, tw, w, lane);
         // Stage arithmetic, slot by slot, with the loads of slot m + D issued
         // before slot m is computed (a ring of D slots of operands), so that
         // the global-memory latency is paid about once per stage.  v[m] is
@@ -398,27 +566,28 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR>
+template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR, bool OR, bool IL>
 hipError_t launch_stream_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
   if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB, YR, OR>), dim3(a.count), dim3(SH::THREADS), 0,
-                     st, a);
+  hipLaunchKernelGGL((rk4_stream<Real, N, E, V, PS, D, PB, YR, OR, IL>), dim3(a.count),
+                     dim3(SH::THREADS), 0, st, a);
   return hipGetLastError();
 }
 
 // kind 13; two complex values of class workspace per mode (k_1, then the
 // partial update; k_2, then u_4); no reverse sweep (the adjoint uses another
-// variant of the size).  The tuning field holds D, plus 16 with PB, 32 with YR
-// and 64 with OR.
+// variant of the size).  The tuning field holds D, plus 16 with PB, 32 with YR,
+// 64 with OR and 128 with IL.
 template <typename Real, int N, int E, int V, int PS, int D, bool PB, bool YR = false,
-          bool OR = false>
+          bool OR = false, bool IL = false>
 constexpr Variant stream_variant() {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS,
-                 D + 16 * PB + 32 * YR + 64 * OR, 13, SH::IPB, SH::THREADS, SH::LDS_BYTES,
-                 &launch_stream_fwd<Real, N, E, V, PS, D, PB, YR, OR>, nullptr, 2};
+                 D + 16 * PB + 32 * YR + 64 * OR + 128 * IL, 13, SH::IPB, SH::THREADS,
+                 SH::LDS_BYTES, &launch_stream_fwd<Real, N, E, V, PS, D, PB, YR, OR, IL>, nullptr,
+                 2};
 }
 
 // The interaction-picture RK4 of cme_rk4ip.hip (its step is written out
@@ -433,7 +602,7 @@ constexpr Variant stream_variant() {
 //   stage 4: y' = P2 Q + h/6 q      -> the state array
 // (P1 = D exp(-i int_t0^tm sigma), P2 = D exp(-i int_tm^t1 sigma)): 224 bytes
 // of global traffic per mode and step in FP64.
-template <typename Real, int N, int E, int V, int PS, int D>
+template <typename Real, int N, int E, int V, int PS, int D, bool IL = false>
 __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     rk4ip_stream(RunArgs a) {
   constexpr int TP = 0;
@@ -460,8 +629,13 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   const __amdgpu_buffer_rsrc_t rD = buf_rsrc(work + 2 * N, N * CB);
   const int i0 = lane + 64 * w;  // slot m: mode i0 + N1 m
 
-  StreamTw<N, E, V, true, Real> tw;
-  load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  static_assert(!IL || (N == S16<Real>::N && E == S16<Real>::E && V == 2 && WP::W == 8),
+                "the 16 x 512 layout is N = 8192 at 16 modes per thread");
+  std::conditional_t<IL, S16Tw<Real>, StreamTw<N, E, V, true, Real>> tw;
+  if constexpr (IL)
+    load_s16_twiddles(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  else
+    load_stream_twiddles<N, E, V>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   const double h = a.h;
   cx<Real> v[E];
@@ -495,13 +669,15 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
     const cx<Real> c2 = {(Real)cs, (Real)sn};
     sfor<0, 4>([&](auto si) {
       constexpr int s = decltype(si)::value;
-      stream_fwdpath<N, E, V, +1, PS, !SH::TWO, true>(v, X, tw, w, lane);
+      if constexpr (IL) s16_inv<+1, !SH::TWO>(v, X, tw, w, lane);
+      else stream_fwdpath<N, E, V, +1, PS, !SH::TWO, true>(v, X, tw, w, lane);
       sfor<0, E>([&](auto mi) {
         constexpr int m = decltype(mi)::value;
         const Real p = v[m].re * v[m].re + v[m].im * v[m].im;
         v[m] = {p * v[m].re, p * v[m].im};
       });
-      stream_backpath<N, E, V, -1, PS, true>(v, X, Y, tw, w, lane);
+      if constexpr (IL) s16_fwd<-1>(v, X, Y, tw, w, lane);
+      else stream_backpath<N, E, V, -1, PS, true>(v, X, Y, tw, w, lane);
       struct Ops {
         cx<Real> y, w1, w2, dm;
       };
@@ -560,27 +736,34 @@ __global__ void __launch_bounds__((WaveShape<Real, N, E, V, PS, 0>::THREADS))
   if (bad) atomicOr(&a.flags[id], 1);
 }
 
-template <typename Real, int N, int E, int V, int PS, int D>
+template <typename Real, int N, int E, int V, int PS, int D, bool IL = false>
 hipError_t launch_stream_ip_fwd(const RunArgs &a, hipStream_t st) {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
   if (a.stages != nullptr || a.work == nullptr) return hipErrorInvalidValue;
   if (a.count <= 0 || a.n_steps <= 0) return hipSuccess;
-  hipLaunchKernelGGL((rk4ip_stream<Real, N, E, V, PS, D>), dim3(a.count), dim3(SH::THREADS), 0,
+  hipLaunchKernelGGL((rk4ip_stream<Real, N, E, V, PS, D, IL>), dim3(a.count), dim3(SH::THREADS), 0,
                      st, a);
   return hipGetLastError();
 }
 
 // kind 14; three complex values of class workspace per mode (W1, W2 and the
-// per-mode factor D); no reverse sweep.  The tuning field holds D.
-template <typename Real, int N, int E, int V, int PS, int D>
+// per-mode factor D); no reverse sweep.  The tuning field holds D, plus 128
+// with IL.
+template <typename Real, int N, int E, int V, int PS, int D, bool IL = false>
 constexpr Variant stream_ip_variant() {
   using SH = WaveShape<Real, N, E, V, PS, 0>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D, 14, SH::IPB,
-                 SH::THREADS, SH::LDS_BYTES, &launch_stream_ip_fwd<Real, N, E, V, PS, D>, nullptr,
-                 3};
+  return Variant{std::is_same<Real, double>::value ? 0 : 1, N, E, V, PS, D + 128 * IL, 14,
+                 SH::IPB, SH::THREADS, SH::LDS_BYTES,
+                 &launch_stream_ip_fwd<Real, N, E, V, PS, D, IL>, nullptr, 3};
 }
 
-// The first of each precision is the default.  Measured, us per step for 1,
+// The first of each precision is the default: the 16 x 512 layout (IL).
+// Measured, us per step for 1 / 16 / 128 instances (per-mode kappa): FP64 IL
+// D = 2 47.2 / 47.1 / 54.0, IL D = 1 47.6 / 47.5 / 55.0, against the
+// two-level OR PB D = 1 52.3 / 52.7 / 57.6; FP32 IL 27.3 / 27.5 (100) / 27.4
+// against 31.3 / 31.4 / 31.5; interaction picture FP64 IL 44.3 / 48.6 (64) /
+// 52.6 against 50.0 / 53.5 / 55.8, FP32 IL 32.0 (16) / 32.9 (100) / 33.2.
+// The two-level figures, us per step for 1,
 // 100 and 128 instances with per-mode kappa (kappa the same for every mode):
 // FP64 OR PB D = 1 52.1 / 56.7 / 57.8 (49.0 / 53.6 / 55.7; 255 VGPRs, no
 // spills), OR PB D = 2 52.1 / 56.3 / 57.1 (48.9 / 53.2 / 54.8; spills 36
@@ -598,6 +781,9 @@ constexpr Variant stream_ip_variant() {
 // 63.5 / 78.9 / 96.8; repeated runs move each figure by up to 2 us); FP32
 // D = 4 35.9 / 35.9 / 36.1 / 36.4, D = 2 35.9 / 35.9 / 36.1 / 36.9.
 static const Variant kStreamVariants[] = {
+    stream_variant<double, 8192, 16, 2, 3, 2, true, false, true, true>(),
+    stream_variant<double, 8192, 16, 2, 3, 1, true, false, true, true>(),
+    stream_variant<float, 8192, 16, 2, 3, 4, true, true, true, true>(),
     stream_variant<double, 8192, 16, 2, 3, 1, true, false, true>(),
     stream_variant<double, 8192, 16, 2, 3, 2, true, false, true>(),
     stream_variant<double, 8192, 16, 2, 3, 2, true>(),
@@ -606,8 +792,10 @@ static const Variant kStreamVariants[] = {
     stream_variant<float, 8192, 16, 2, 3, 2, true, true, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, true, true>(),
     stream_variant<float, 8192, 16, 2, 3, 4, false>(),
+    stream_ip_variant<double, 8192, 16, 2, 3, 2, true>(),
     stream_ip_variant<double, 8192, 16, 2, 3, 2>(),
     stream_ip_variant<double, 8192, 16, 2, 3, 1>(),
+    stream_ip_variant<float, 8192, 16, 2, 3, 4, true>(),
     stream_ip_variant<float, 8192, 16, 2, 3, 4>(),
     stream_ip_variant<float, 8192, 16, 2, 3, 2>(),
 };
