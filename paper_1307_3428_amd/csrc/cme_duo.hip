@@ -544,21 +544,28 @@ template <typename Real> struct D8L {
   static constexpr int CTX = 8 * RL;
 };
 
-// cross twiddles x[k1] = exp(-2 pi i c k1 / N); the multiply-add level
-// twiddles of pass 1 (radix 8, base exp(-2 pi i (t mod 8) / 64)) and of the
-// two radix-4 butterflies of pass 2 (bases exp(-2 pi i (t + 32 q) / 256))
-template <typename Real> struct D8Tw {
-  cx<Real> x[8];
+// cross twiddles x[k1] = exp(-2 pi i c k1 / N) (XP; else x[1] only, the
+// powers formed where they are applied, for kernels short of registers);
+// the multiply-add level twiddles of pass 1 (radix 8, base
+// exp(-2 pi i (t mod 8) / 64)) and of the two radix-4 butterflies of pass 2
+// (bases exp(-2 pi i (t + 32 q) / 256))
+template <typename Real, bool XP = true> struct D8Tw {
+  cx<Real> x[XP ? 8 : 2];
   cx<Real> p1[8];
   cx<Real> p2[2][4];
 };
+template <typename Real, bool XP>
+__device__ __forceinline__ void d8_cross_twiddles(cx<Real> (&t)[8], const D8Tw<Real, XP> &tw) {
+  if constexpr (XP) sfor<1, 8>([&](auto ki) { t[decltype(ki)::value] = tw.x[decltype(ki)::value]; });
+  else pow_fill<8>(t, tw.x[1]);
+}
 
 // tab[i] = exp(-2 pi i i / 2048)
-template <typename Real>
-__device__ __forceinline__ void load_d8_twiddles(D8Tw<Real> &tw, const cx<Real> *__restrict__ tab,
-                                                 int w, int l) {
+template <typename Real, bool XP>
+__device__ __forceinline__ void load_d8_twiddles(D8Tw<Real, XP> &tw,
+                                                 const cx<Real> *__restrict__ tab, int w, int l) {
   const int c = 64 * w + l, t = l >> 1;
-  sfor<1, 8>([&](auto ki) {
+  sfor<1, (XP ? 8 : 2)>([&](auto ki) {
     constexpr int k1 = decltype(ki)::value;
     tw.x[k1] = tab[(c * k1) & (D8::N - 1)];
   });
@@ -572,8 +579,8 @@ __device__ __forceinline__ void load_d8_twiddles(D8Tw<Real> &tw, const cx<Real> 
   level(tw.p2[0], 4, 8 * t);
   level(tw.p2[1], 4, 8 * (t + 32));
 }
-template <typename Real>
-__device__ __forceinline__ void load_twiddle_source(D8Tw<Real> &tw, const cx<Real> *tab, int w,
+template <typename Real, bool XP>
+__device__ __forceinline__ void load_twiddle_source(D8Tw<Real, XP> &tw, const cx<Real> *tab, int w,
                                                     int l) {
   load_d8_twiddles(tw, tab, w, l);
 }
@@ -605,12 +612,12 @@ template <typename Real> __device__ __forceinline__ void d8_lane_exchange(cx<Rea
 
 // passes 1 and 2 of a sub-transform (pass 2: radix-4 butterflies q = 0, 1 on
 // slots q + 2 s, positions t + 32 q + 64 s), natural order out
-template <int S, typename Real>
-__device__ __forceinline__ void d8_pass1(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+template <int S, typename Real, typename TW>
+__device__ __forceinline__ void d8_pass1(cx<Real> (&v)[8], const TW &tw) {
   dft_reg_fma<8, S>(v, tw.p1);
 }
-template <int S, typename Real>
-__device__ __forceinline__ void d8_pass2(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+template <int S, typename Real, typename TW>
+__device__ __forceinline__ void d8_pass2(cx<Real> (&v)[8], const TW &tw) {
   sfor<0, 2>([&](auto qi) {
     constexpr int q = decltype(qi)::value;
     cx<Real> z[4];
@@ -650,23 +657,27 @@ __device__ __forceinline__ void d8_cross_get(cx<Real> (&v)[8], const cx<Real> *X
   const int o = lpad<3>(c);
   sfor<0, 8>([&](auto ki) { v[decltype(ki)::value] = X[decltype(ki)::value * D8L<Real>::RL + o]; });
 }
-template <int S, typename Real>
-__device__ __forceinline__ void d8_cross_inv(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
+template <int S, typename Real, typename TW>
+__device__ __forceinline__ void d8_cross_inv(cx<Real> (&v)[8], const TW &tw) {
   dft_reg<8, S>(v);
-  sfor<1, 8>([&](auto ki) { v[decltype(ki)::value] = ctw<S>(v[decltype(ki)::value], tw.x[decltype(ki)::value]); });
+  cx<Real> t[8];
+  d8_cross_twiddles(t, tw);
+  sfor<1, 8>([&](auto ki) { v[decltype(ki)::value] = ctw<S>(v[decltype(ki)::value], t[decltype(ki)::value]); });
 }
-template <int S, typename Real>
-__device__ __forceinline__ void d8_cross_fwd(cx<Real> (&v)[8], const D8Tw<Real> &tw) {
-  sfor<1, 8>([&](auto ki) { v[decltype(ki)::value] = ctw<S>(v[decltype(ki)::value], tw.x[decltype(ki)::value]); });
+template <int S, typename Real, typename TW>
+__device__ __forceinline__ void d8_cross_fwd(cx<Real> (&v)[8], const TW &tw) {
+  cx<Real> t[8];
+  d8_cross_twiddles(t, tw);
+  sfor<1, 8>([&](auto ki) { v[decltype(ki)::value] = ctw<S>(v[decltype(ki)::value], t[decltype(ki)::value]); });
   dft_reg<8, S>(v);
 }
 
 // Two inverse paths (mode order in, sub-transform order out) in contexts XA,
 // XB, the LDS traffic of one sequence interleaved with the other's
 // arithmetic.  PRE: barrier first (single buffer set).
-template <int S, bool PRE, int NV, typename Real>
+template <int S, bool PRE, int NV, typename Real, typename TW>
 __device__ __forceinline__ void d8_inv2(cx<Real> (&va)[8], cx<Real> (&vb)[8], cx<Real> *XA,
-                                        cx<Real> *XB, const D8Tw<Real> &tw, int w, int l) {
+                                        cx<Real> *XB, const TW &tw, int w, int l) {
   if constexpr (PRE) __syncthreads();
   const int c = 64 * w + l, t = l >> 1, reg = (2 * w + (l & 1)) * D8L<Real>::RL;
   __builtin_amdgcn_sched_barrier(0);
@@ -700,9 +711,9 @@ __device__ __forceinline__ void d8_inv2(cx<Real> (&va)[8], cx<Real> (&vb)[8], cx
 }
 
 // Two forward paths (sub-transform order in, mode order out).
-template <int S, bool PRE, int NV, typename Real>
+template <int S, bool PRE, int NV, typename Real, typename TW>
 __device__ __forceinline__ void d8_fwd2(cx<Real> (&va)[8], cx<Real> (&vb)[8], cx<Real> *XA,
-                                        cx<Real> *XB, const D8Tw<Real> &tw, int w, int l) {
+                                        cx<Real> *XB, const TW &tw, int w, int l) {
   if constexpr (PRE) __syncthreads();
   const int c = 64 * w + l, t = l >> 1, reg = (2 * w + (l & 1)) * D8L<Real>::RL;
   __builtin_amdgcn_sched_barrier(0);
@@ -762,14 +773,20 @@ template <int LY, int N, int E> __device__ __forceinline__ int duo_mode(int w, i
   if constexpr (LY == 1) return D8::mode(w, l, m);
   else return WavePlan<N, E, 1, 0>::mode(w, l, m);
 }
+// storage position of slot m on the transformed side (the stage records of
+// the inverse transforms): a bijection onto [0, N) with lanes contiguous,
+// the same in the forward recompute and the reverse sweep of a layout
+template <int LY, int N, int E> __device__ __forceinline__ int duo_tslot(int w, int l, int m) {
+  if constexpr (LY == 1) return l + 64 * (w + 4 * m);
+  else return WavePlan<N, E, 1, 0>::tslot(w, l, m);
+}
 
-// REC: record the stage inputs and inverse transforms for the adjoint (two-
-// level layout only: the reverse sweeps read its slot order)
+// REC: record the stage inputs (mode order) and inverse transforms (slot
+// order duo_tslot of the layout, which its reverse sweep reads)
 template <typename Real, int N, int E, int PS, int NV, int FT, bool REC, int LY = 0>
 __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_duo(RunArgs a) {
   using SH = DuoShape<Real, N, E, PS, LY>;
   using WP = WavePlan<N, E, 1, 0>;
-  static_assert(!(REC && LY == 1), "no stage records in the 8 x 256 layout");
   constexpr bool ONESET = SH::NSET == 1;
   __shared__ cx<Real> lds[SH::PER_INST];
 
@@ -832,13 +849,13 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_d
   auto rec_u = [&](int64_t n, int s, auto mi, const cx<Real> &u) {
     if constexpr (REC) {
       constexpr int m = decltype(mi)::value;
-      stages[stage_offset(n, s, a.total) + d.offset + WP::mode(w, lane, m)] = u;
+      stages[stage_offset(n, s, a.total) + d.offset + duo_mode<LY, N, E>(w, lane, m)] = u;
     }
   };
   auto rec_a = [&](int64_t n, int s, auto mi, const cx<Real> &x) {
     if constexpr (REC) {
       constexpr int m = decltype(mi)::value;
-      stages[stage_offset(n, s, a.total) + a.total + d.offset + WP::tslot(w, lane, m)] = x;
+      stages[stage_offset(n, s, a.total) + a.total + d.offset + duo_tslot<LY, N, E>(w, lane, m)] = x;
     }
   };
 
@@ -958,10 +975,9 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_d
 // sums from it and the stage inputs u_s afterwards, so neither the
 // accumulators nor u_s occupy registers here.  The time-domain records a_s
 // are loaded a round before they are needed.
-template <typename Real, int N, int E, int PS, int NV, int FT>
-__global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_reverse(AdjArgs a) {
-  using SH = DuoShape<Real, N, E, PS>;
-  using WP = WavePlan<N, E, 1, 0>;
+template <typename Real, int N, int E, int PS, int NV, int FT, int LY = 0>
+__global__ void __launch_bounds__((DuoShape<Real, N, E, PS, LY>::THREADS)) rk4_duo_reverse(AdjArgs a) {
+  using SH = DuoShape<Real, N, E, PS, LY>;
   constexpr bool ONESET = SH::NSET == 1;
   __shared__ cx<Real> lds[SH::PER_INST];
 
@@ -977,17 +993,21 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
   const cx<Real> *stages = reinterpret_cast<const cx<Real> *>(a.stages);
 
   std::conditional_t<
-      FT >= 2, FmaTw<N, E, Real, FT == 2>,
-      std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>>>
+      LY == 1, D8Tw<Real, false>,
+      std::conditional_t<FT >= 2, FmaTw<N, E, Real, FT == 2>,
+                         std::conditional_t<FT == 1, FullTw<N, E, Real>, LeanTw<N, E, Real>>>>
       tw;
-  load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  if constexpr (LY == 1)
+    load_twiddle_source(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
+  else
+    load_twiddle_source<N, E>(tw, reinterpret_cast<const cx<Real> *>(a.twiddle), w, lane);
 
   cx<Real> yb1[E], yb[E], k2[E], va[E], vb[E], ra[E], rb[E];
   Real lr[E];
   double om[E];
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    const int i = WP::mode(w, lane, m);
+    const int i = duo_mode<LY, N, E>(w, lane, m);
     yb1[m] = gA[i];
     lr[m] = (Real)(-0.5 * kap[i]);
     om[m] = omg[i];
@@ -1015,17 +1035,17 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
   // kbar_s of step n, for the parameter cotangents (launch_adj_params)
   auto store_kbar = [&](int64_t n, int s, auto mi, const cx<Real> &kv) {
     constexpr int m = decltype(mi)::value;
-    kbar[(n * 4 + s) * a.total + d.offset + WP::mode(w, lane, m)] = kv;
+    kbar[(n * 4 + s) * a.total + d.offset + duo_mode<LY, N, E>(w, lane, m)] = kv;
   };
   // record addresses are rebuilt at each use (an opaque base) rather than
   // kept in registers for the whole run
   auto load_a = [&](cx<Real> (&dst)[E], int64_t n, int s) {
     const cx<Real> *rec = stages + stage_offset(n, s, a.total) + a.total + d.offset;
-    int base = WP::tslot(w, lane, 0);
+    int base = duo_tslot<LY, N, E>(w, lane, 0);
     asm volatile("" : "+v"(base));
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
-      dst[m] = rec[base + (WP::tslot(w, lane, m) - WP::tslot(w, lane, 0))];
+      dst[m] = rec[base + (duo_tslot<LY, N, E>(w, lane, m) - duo_tslot<LY, N, E>(w, lane, 0))];
     });
   };
 
@@ -1042,7 +1062,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       va[m] = yb1[m];
       vb[m] = clin(cx<Real>{hw1 * yb1[m].re, hw1 * yb1[m].im}, mi, s4);
     });
-    lean_fwd2<N, E, +1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA0, XB0, tw, w, lane);
+    if constexpr (LY == 1) d8_inv2<+1, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    else lean_fwd2<N, E, +1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> q4 = kerr_t(mig(cx<Real>{hw1 * va[m].re, hw1 * va[m].im}), ra[m]);
@@ -1052,7 +1073,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       vb[m] = kerr_t(mig(x3), rb[m]);
     });
     // ---- B: DFT(q_4), DFT(q_3)
-    lean_back2<N, E, -1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA1, XB1, tw, w, lane);
+    if constexpr (LY == 1) d8_fwd2<-1, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    else lean_back2<N, E, -1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> k4 = {hw1 * yb1[m].re, hw1 * yb1[m].im};
@@ -1073,7 +1095,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
     //         IDFT(h/6 ybar' + h/2 conj(L_2) kbar_2) = h/6 Ybar + h/2 P_2
     load_a(ra, nn, 1);
     load_a(rb, nn, 0);
-    lean_fwd2<N, E, +1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA0, XB0, tw, w, lane);
+    if constexpr (LY == 1) d8_inv2<+1, ONESET, NV>(va, vb, XA0, XB0, tw, w, lane);
+    else lean_fwd2<N, E, +1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA0, XB0, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> q2 = kerr_t(mig(va[m]), ra[m]);
@@ -1082,7 +1105,8 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
       vb[m] = kerr_t(mig(x1), rb[m]);
     });
     // ---- D: DFT(q_2), DFT(q_1)
-    lean_back2<N, E, -1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA1, XB1, tw, w, lane);
+    if constexpr (LY == 1) d8_fwd2<-1, ONESET, NV>(va, vb, XA1, XB1, tw, w, lane);
+    else lean_back2<N, E, -1, PS, ONESET, NV, lx_ok<N, E>()>(va, vb, XA1, XB1, tw, w, lane);
     sfor<0, E>([&](auto mi) {
       constexpr int m = decltype(mi)::value;
       const cx<Real> c2 = clin(k2[m], mi, s2);
@@ -1097,7 +1121,7 @@ __global__ void __launch_bounds__((DuoShape<Real, N, E, PS>::THREADS)) rk4_duo_r
   }
   sfor<0, E>([&](auto mi) {
     constexpr int m = decltype(mi)::value;
-    const int i = WP::mode(w, lane, m);
+    const int i = duo_mode<LY, N, E>(w, lane, m);
     gA[i] = yb1[m];
   });
 }
@@ -1146,12 +1170,23 @@ hipError_t launch_duo_adj(const AdjArgs &a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// the 8 x 256 layout: no stage records (its adjoint runs on a two-level variant)
+// the 8 x 256 layout, forward (with stage records for its reverse sweep) and
+// reverse
 template <typename Real, int NV>
 hipError_t launch_duo8_fwd(const RunArgs &a, hipStream_t st) {
   using SH = DuoShape<Real, D8::N, D8::E, 3, 1>;
-  if (a.stages) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((rk4_duo<Real, D8::N, D8::E, 3, NV, 2, false, 1>), dim3(a.count),
+  if (a.stages)
+    hipLaunchKernelGGL((rk4_duo<Real, D8::N, D8::E, 3, NV, 2, true, 1>), dim3(a.count),
+                       dim3(SH::THREADS), 0, st, a);
+  else
+    hipLaunchKernelGGL((rk4_duo<Real, D8::N, D8::E, 3, NV, 2, false, 1>), dim3(a.count),
+                       dim3(SH::THREADS), 0, st, a);
+  return hipGetLastError();
+}
+template <typename Real, int NV>
+hipError_t launch_duo8_adj(const AdjArgs &a, hipStream_t st) {
+  using SH = DuoShape<Real, D8::N, D8::E, 3, 1>;
+  hipLaunchKernelGGL((rk4_duo_reverse<Real, D8::N, D8::E, 3, NV, 2, 1>), dim3(a.count),
                      dim3(SH::THREADS), 0, st, a);
   return hipGetLastError();
 }
@@ -1210,8 +1245,12 @@ constexpr Variant duo_variant() {
 // 8 x 256 layout: reported with two sub-transforms per wave (v = 2)
 template <typename Real, int NV> constexpr Variant duo8_variant() {
   using SH = DuoShape<Real, D8::N, D8::E, 3, 1>;
-  return Variant{std::is_same<Real, double>::value ? 0 : 1, D8::N, D8::E, 2, 3, NV + 32, 2, 1,
-                 SH::THREADS, SH::LDS_BYTES, &launch_duo8_fwd<Real, NV>, nullptr};
+  if constexpr (std::is_same<Real, double>::value)
+    return Variant{0, D8::N, D8::E, 2, 3, NV + 32, 2, 1, SH::THREADS, SH::LDS_BYTES,
+                   &launch_duo8_fwd<Real, NV>, &launch_duo8_adj<Real, NV>, 0, 1};
+  else  // FP32 plans have no adjoint
+    return Variant{1, D8::N, D8::E, 2, 3, NV + 32, 2, 1, SH::THREADS, SH::LDS_BYTES,
+                   &launch_duo8_fwd<Real, NV>, nullptr};
 }
 
 // The first entry of a size is its default.  N = 512 and 1024 run four
@@ -1226,8 +1265,10 @@ template <typename Real, int NV> constexpr Variant duo8_variant() {
 // instructions per wave and step in place of 2967 with every power held:
 // 9.55); FP32 8 x 256 7.07, two-level FT = 2 7.08 (7.52 with every power
 // held).  At N = 1024 (radix-4 passes) the multiply-add form saves 7% of the
-// instructions and no time, so it is not built there.  The 8 x 256 layout
-// records no stage inputs: its adjoint runs on the two-level variant.
+// instructions and no time, so it is not built there.  The 8 x 256
+// layout's adjoint runs in the same layout (reverse sweep with the
+// cross-wave powers formed on use): 61.9 against 64.6 ms on the two-level
+// variant for the N = 2048 gradient workload.
 // N = 512 and 1024 take the last sub-transform exchange in registers
 // (lane_exchange4): 256 x N=1024 6.78 -> 6.07 us per step (FP32 4.56 ->
 // 4.29), 256 x N=512 4.93 -> 4.86 (FP32 3.91 -> 3.81).
