@@ -763,6 +763,9 @@ constexpr Variant stream_ip_variant() {
 // two-level OR PB D = 1 52.3 / 52.7 / 57.6; FP32 IL 27.3 / 27.5 (100) / 27.4
 // against 31.3 / 31.4 / 31.5; interaction picture FP64 IL 44.3 / 48.6 (64) /
 // 52.6 against 50.0 / 53.5 / 55.8, FP32 IL 32.0 (16) / 32.9 (100) / 33.2.
+// FP64 IL D = 3 ran 1-2% faster than D = 2 (48.4 against 49.3 at 128
+// instances, uniform kappa) but spills 12 bytes per lane (D = 4: 32), and
+// FP32 IL D = 2 or 8 changed nothing; none of them is built.
 // The two-level figures, us per step for 1,
 // 100 and 128 instances with per-mode kappa (kappa the same for every mode):
 // FP64 OR PB D = 1 52.1 / 56.7 / 57.8 (49.0 / 53.6 / 55.7; 255 VGPRs, no
