@@ -1263,8 +1263,9 @@ template <typename Real, int NV> constexpr Variant duo8_variant() {
 // 256 x N=2048 (sweep workload, us per step): 8 x 256 NV = 5 / 6 / 7 / 8:
 // 9.12 / 9.08 / 9.04 / 9.04; two-level FT = 2 NV = 5: 9.38 (2747 VALU
 // instructions per wave and step in place of 2967 with every power held:
-// 9.55); FP32 8 x 256 7.07, two-level FT = 2 7.08 (7.52 with every power
-// held).  At N = 1024 (radix-4 passes) the multiply-add form saves 7% of the
+// 9.55); FP32 8 x 256 NV = 5 / 7 / 8 / 12 / 16: 7.07 / 7.03 / 6.97 / 6.99 /
+// 7.00, two-level FT = 2 7.09 (7.52 with every power held); FP64 NV = 10 and
+// 12: 8.99 and 9.28.  At N = 1024 (radix-4 passes) the multiply-add form saves 7% of the
 // instructions and no time, so it is not built there.  The 8 x 256
 // layout's adjoint runs in the same layout (reverse sweep with the
 // cross-wave powers formed on use): 61.9 against 64.6 ms on the two-level
@@ -1291,8 +1292,8 @@ static const Variant kDuoVariantsF32[] = {
     duo_variant<float, 512, 4, 2, 4, 1, true>(), duo_variant<float, 1024, 4, 2, 5, 1, true>(),
     duo_variant<float, 512, 4, 2, 4, 1>(),  duo_variant<float, 1024, 4, 2, 5, 1>(),
     duo_variant<float, 1024, 4, 2, 4, 1>(), duo_variant<float, 1024, 8, 3, 5, 1>(),
+    duo8_variant<float, 8>(),
     duo_variant<float, 2048, 8, 3, 5, 2>(), duo_variant<float, 2048, 8, 3, 4, 2>(),
-    duo8_variant<float, 5>(),
     duo_variant<float, 2048, 8, 3, 5, 1>(), duo_variant<float, 2048, 8, 3, 4, 1>(),
 };
 
