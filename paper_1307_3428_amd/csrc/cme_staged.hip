@@ -589,7 +589,7 @@ const Variant kStagedVariants[] = {
     staged_variant<16384, 128, 8, 4>(), staged_variant<32768, 256, 8, 8>(),
     staged_variant<32768, 256, 8, 4>(), staged_variant<65536, 256, 8, 8>(),
     staged_variant<65536, 256, 8, 4>(),
-    // FP32 state and transforms (FP64 stage arithmetic)
+    // FP32 state, transforms and stage arithmetic (FP64 only in the time-dependent coefficients)
     staged_variant<8192, 128, 8, 8, false, float>(),  staged_variant<16384, 128, 8, 8, false, float>(),
     staged_variant<32768, 256, 8, 8, false, float>(), staged_variant<65536, 256, 8, 8, false, float>(),
 };
@@ -618,7 +618,7 @@ const Variant kStagedPadVariants[] = {
 const Variant kStagedIpVariants[] = {
     staged_variant<8192, 128, 8, 8, true>(),  staged_variant<16384, 128, 8, 8, true>(),
     staged_variant<32768, 256, 8, 8, true>(), staged_variant<65536, 256, 8, 8, true>(),
-    // FP32 state and transforms above 8192 (FP64 stage arithmetic)
+    // FP32 above 8192: state, transforms and stage arithmetic (FP64 only in the propagator's phase)
     staged_variant<16384, 128, 8, 8, true, float>(), staged_variant<32768, 256, 8, 8, true, float>(),
     staged_variant<65536, 256, 8, 8, true, float>(),
 };
