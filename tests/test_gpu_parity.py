@@ -126,6 +126,46 @@ def test_stream_kernel_uniform_and_mixed_kappa(cme, orc, prec, kid):
     assert not st.any()
 
 
+def _duo8_params():
+    try:
+        from paper_1307_3428_amd import cme as C
+        return [(prec, k) for prec in (C.CME_F64, C.CME_F32) for k in C.cme_list_kernels(prec, 2048)
+                if C.cme_kernel_info(k)["kind"] == 2 and C.cme_kernel_info(k)["sub_transforms"] == 2]
+    except Exception:
+        return [(0, 0)]
+
+
+@pytest.mark.parametrize("prec,kid", _duo8_params())
+def test_duo_8x256_uniform_and_mixed_kappa(cme, orc, prec, kid):
+    """The N = 2048 paired kernels in the 8 x 256 layout hold -kappa/2 as one
+    value for instances whose kappa is the same for every mode: two such
+    instances beside two with per-mode kappa in one launch, against the
+    oracle, whole state and sidebands."""
+    info = cme.cme_kernel_info(kid)
+    print(f"variant {info['name']}", flush=True)
+    insts = (W.random_batch(4201, [2048, 2048], noise=1.0, random_kappa=False)
+             + W.random_batch(4202, [2048, 2048], noise=1.0))
+    for inst in insts:
+        inst.a0 = inst.a0 / math.sqrt(inst.n_modes)
+        inst.a0[inst.n_modes // 2] += 0.5
+    assert all(np.all(x.kappa == x.kappa[0]) for x in insts[:2])
+    assert not any(np.all(x.kappa == x.kappa[0]) for x in insts[2:])
+    p = W.pack(insts)
+    steps, h = 6, 0.01
+    if prec == cme.CME_F64:
+        y, st = gpu_run(cme, p, h, steps, step0=3, kid=kid, n=2048)
+        tol = 1e-13
+    else:
+        y, st = gpu_run32(cme, p, h, steps, step0=3, kid=kid, n=2048)
+        tol = 2e-6
+    ref, _ = orc.run(p, h, steps, step0=3)
+    for i in range(p.batch):
+        e = errors(y[p.slice(i)], ref[p.slice(i)])
+        print(f"instance {i}: whole {e['whole']:.2e} sidebands {e['side']:.2e}", flush=True)
+        assert e["whole"] <= tol and e["side"] <= tol, (i, e)
+    assert not st.any()
+
+
 def test_mixed_sizes_in_one_plan(cme, orc):
     sizes = [16, 2048, 64, 128, 16, 1024, 256, 512, 32, 4096]
     insts = moderate_batch(77, sizes)
