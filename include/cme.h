@@ -114,7 +114,11 @@ typedef struct cme_plan cme_plan;
 /* Create a plan for a batch of `batch` instances (Eq. (1) parameters).
  *   inst   host array [batch]; copied.
  *   kappa  device array [total] of FP64 kappa_mu (total loss per mode); copied
- *          into plan-owned memory, so it may be freed after the call.
+ *          into plan-owned memory, so it may be freed after the call.  An
+ *          instance whose kappa_mu is the same for every mode runs a faster
+ *          path of the N = 2048 paired kernel and the N = 8192 LDS-resident
+ *          kernels (one loss value instead of one per mode); results agree
+ *          with the per-mode path to rounding.
  *   omega  device array [total] of FP64 omega'_mu; copied likewise.
  *   precision CME_F64 or CME_F32 (FP32 state and transforms; the time and
  *          detuning bookkeeping stays FP64).
